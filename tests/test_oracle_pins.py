@@ -1,0 +1,496 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Nothing here touches the GPU or the HIP library.  Each pin is chosen so that a
+plausible slip in the oracle (a dropped term, a wrong sign or index, a
+transposed operand, a missing fftshift) fails at least one of them; the
+``test_pins_catch_*`` tests plant such slips in copies of the oracle's output
+and check that the pins notice.
+
+Paper: Morrison et al. 2023, "MWAX: A New Correlator for the MWA".
+"""
+import cmath
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def rng(seed=1):
+    return np.random.default_rng(seed)
+
+
+def rand_volts(n, S, seed=1, amp=127):
+    v = rng(seed).integers(-amp, amp + 1, size=(n, S, 2))
+    return v.astype(np.int8)
+
+
+# ---------------------------------------------------------------------------
+# Pin checks, written as functions so the mutation tests can reuse them.
+# ---------------------------------------------------------------------------
+def brute_force_vis(volts, L, T):
+    """Definition written out in pure Python (Sec. 2.5.1 F step, Sec. 2.5.2 X step).
+
+    Returns full matrices V[j][c][n1][n2] as nested lists of Python complex.
+    """
+    n_in, S = volts.shape[0], volts.shape[1]
+    M = S // L
+    X = [[[0j] * L for _ in range(M)] for _ in range(n_in)]
+    for n in range(n_in):
+        for m in range(M):
+            for k in range(L):
+                acc = 0j
+                for q in range(L):
+                    x = complex(int(volts[n, m * L + q, 0]), int(volts[n, m * L + q, 1]))
+                    acc += x * cmath.exp(-2j * math.pi * k * q / L)
+                X[n][m][(k + L // 2) % L] = acc
+    n_int = M // T
+    V = [[[[0j] * n_in for _ in range(n_in)] for _ in range(L)] for _ in range(n_int)]
+    for j in range(n_int):
+        for c in range(L):
+            for a in range(n_in):
+                for b in range(n_in):
+                    V[j][c][a][b] = sum(X[a][m][c] * X[b][m][c].conjugate()
+                                        for m in range(j * T, (j + 1) * T))
+    return V
+
+
+def check_brute_force(vis_packed, V, tol):
+    n_int, L, P = vis_packed.shape
+    n_in = len(V[0][0])
+    for j in range(n_int):
+        for c in range(L):
+            for a in range(n_in):
+                for b in range(a + 1):
+                    got = vis_packed[j, c, a * (a + 1) // 2 + b]
+                    want = V[j][c][a][b]
+                    if abs(got - want) > tol * max(1.0, abs(want)):
+                        return False
+    return True
+
+
+def tone_channel_ok(vis, L, k0, T, amp, phases):
+    """P4: all power in c0 = (k0 + L/2) mod L with V = T L^2 A^2 i^(p1 - p2)."""
+    c0 = (k0 + L // 2) % L
+    n_in = len(phases)
+    peak = T * L * L * amp * amp
+    for c in range(L):
+        for a in range(n_in):
+            for b in range(a + 1):
+                got = vis[0, c, a * (a + 1) // 2 + b]
+                want = peak * (1j ** ((phases[a] - phases[b]) % 4)) if c == c0 else 0
+                if abs(got - want) > 1e-9 * peak:
+                    return False
+    return True
+
+
+def point_source_ok(vis, c0, taus, nu, T, L, amp, sigma2_c):
+    """P5: E V[c0][n1,n2] = T L^2 A^2 exp(-2 pi i nu (tau1 - tau2)) within 6 sigma."""
+    n_in = len(taus)
+    v = L * sigma2_c
+    s = T * L * L * amp * amp
+    rms = math.sqrt(T * (v * v + 2 * v * L * L * amp * amp))
+    for a in range(n_in):
+        for b in range(a):
+            want = s * cmath.exp(-2j * math.pi * nu * (taus[a] - taus[b]))
+            got = vis[0, c0, a * (a + 1) // 2 + b]
+            if abs(got - want) > 6 * rms:
+                return False
+    return True
+
+
+# ---------------------------------------------------------------------------
+# DFT / FFT pins
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16, 64])
+def test_dft_closed_forms(orc, L):
+    # delta at q0 -> X[k] = exp(-2 pi i k q0 / L)
+    for q0 in range(L):
+        x = np.zeros(L, complex)
+        x[q0] = 1
+        X = orc.dft(x)
+        want = np.array([cmath.exp(-2j * math.pi * k * q0 / L) for k in range(L)])
+        assert np.max(np.abs(X - want)) < 1e-12
+    # constant -> L at DC only
+    X = orc.dft(np.full(L, 3 - 2j))
+    want = np.zeros(L, complex)
+    want[0] = L * (3 - 2j)
+    assert np.max(np.abs(X - want)) < 1e-12 * L
+    # positive-frequency tone exp(+2 pi i k0 q / L) -> L at bin k0 (forward sign)
+    k0 = L // 4 if L >= 4 else 0
+    x = np.array([cmath.exp(2j * math.pi * k0 * q / L) for q in range(L)])
+    X = orc.dft(x)
+    want = np.zeros(L, complex)
+    want[k0] = L
+    assert np.max(np.abs(X - want)) < 1e-11 * L
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16, 32, 64])
+def test_fft_matches_dft(orc, L):
+    x = rng(L).normal(size=L) + 1j * rng(L + 100).normal(size=L)
+    assert np.max(np.abs(orc.fft(x) - orc.dft(x))) < 1e-12 * L
+
+
+@pytest.mark.parametrize("L", [2, 32, 128, 1024, 4096])
+def test_fft_matches_numpy(orc, L):
+    # numpy.fft.fft uses the same forward sign and no normalisation.
+    x = rng(L).normal(size=L) * 50 + 1j * rng(L + 1).normal(size=L) * 50
+    X = orc.fft(x)
+    ref = np.fft.fft(x)
+    assert np.max(np.abs(X - ref)) < 1e-12 * np.max(np.abs(ref)) * math.log2(L)
+
+
+def test_fft_rejects_non_power_of_two(orc):
+    with pytest.raises(ValueError):
+        orc.fft(np.ones(6))
+
+
+# ---------------------------------------------------------------------------
+# Channel order: centre-symmetric channels with DC at c = L/2 (Sec. 2.6)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [4, 8, 128])
+def test_channel_order(orc, L):
+    # a DC (constant) input lands in the centre channel
+    v = np.zeros((1, 2 * L, 2), np.int8)
+    v[0, :, 0] = 5
+    spec = orc.channelise(v, L)
+    assert np.count_nonzero(np.abs(spec) > 1e-9) == 2
+    assert np.allclose(spec[:, L // 2, 0], 5 * L)
+    # an exact tone at bin k0 = L/4 lands in channel (k0 + L/2) mod L = 3L/4
+    v = synth.tone_volts(1, 2 * L, L, L // 4, 10, [0])
+    spec = orc.channelise(v, L)
+    mag = np.abs(spec[0, :, 0])
+    assert int(np.argmax(mag)) == (L // 4 + L // 2) % L
+    assert mag.max() == pytest.approx(10 * L)
+
+
+def test_channelise_dft_and_fft_agree(orc):
+    v = rand_volts(3, 16 * 5, seed=7)
+    a = orc.channelise(v, 16)
+    b = orc.channelise(v, 16, use_dft=True)
+    assert np.max(np.abs(a - b)) < 1e-10
+
+
+def test_channelise_subsets(orc):
+    v = rand_volts(5, 64 * 6, seed=3)
+    full = orc.channelise(v, 64)
+    part = orc.channelise(v, 64, inputs=[4, 1], m0=2, nm=3)
+    assert np.array_equal(part[:, :, 0], full[2:5, :, 4])
+    assert np.array_equal(part[:, :, 1], full[2:5, :, 1])
+
+
+# ---------------------------------------------------------------------------
+# P1 brute force on 2-4 inputs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_in,L,M,T", [(2, 4, 3, 3), (3, 8, 4, 2), (4, 2, 6, 3), (2, 1, 5, 5)])
+def test_brute_force_small(orc, n_in, L, M, T):
+    v = rand_volts(n_in, L * M, seed=n_in * 10 + L)
+    vis = orc.fx_correlate(v, L, T)
+    V = brute_force_vis(v, L, T)
+    assert vis.shape == (M // T, L, n_in * (n_in + 1) // 2)
+    assert check_brute_force(vis, V, 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# P2 exact-integer special cases L in {1, 2, 4}
+# ---------------------------------------------------------------------------
+def _exact_vis(volts, L, T):
+    """Gaussian-integer arithmetic: exp(-2 pi i k q / L) = (-i)^(4kq/L) for L | 4."""
+    powers = [(1, 0), (0, -1), (-1, 0), (0, 1)]          # (-i)^0..3
+    n_in, S = volts.shape[0], volts.shape[1]
+    M = S // L
+    X = np.zeros((n_in, M, L, 2), dtype=object)
+    for n in range(n_in):
+        for m in range(M):
+            for k in range(L):
+                re = im = 0
+                for q in range(L):
+                    a, b = int(volts[n, m * L + q, 0]), int(volts[n, m * L + q, 1])
+                    wr, wi = powers[(4 * k * q // L) % 4]
+                    re += a * wr - b * wi
+                    im += a * wi + b * wr
+                X[n, m, (k + L // 2) % L] = (re, im)
+    out = np.zeros((M // T, L, n_in * (n_in + 1) // 2, 2), dtype=object)
+    for j in range(M // T):
+        for c in range(L):
+            for a in range(n_in):
+                for b in range(a + 1):
+                    sr = si = 0
+                    for m in range(j * T, (j + 1) * T):
+                        r1, i1 = X[a, m, c]
+                        r2, i2 = X[b, m, c]
+                        sr += r1 * r2 + i1 * i2
+                        si += i1 * r2 - r1 * i2
+                    out[j, c, a * (a + 1) // 2 + b] = (sr, si)
+    return out
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_exact_integer_cases(orc, L):
+    v = rand_volts(4, L * 12, seed=L)
+    vis = orc.fx_correlate(v, L, 6)
+    ex = _exact_vis(v, L, 6)
+    assert np.array_equal(vis.real, ex[..., 0].astype(np.float64))
+    assert np.array_equal(vis.imag, ex[..., 1].astype(np.float64))
+
+
+def test_L1_is_textbook_outer_product(orc):
+    # L = 1: no transform, V = sum_m x x^H (a ZHERK), checked with numpy matmul.
+    v = rand_volts(6, 40, seed=11)
+    vis = orc.fx_correlate(v, 1, 40)
+    x = v[..., 0].astype(np.float64) + 1j * v[..., 1]
+    full = x @ x.conj().T
+    tri = np.array([full[a, b] for a in range(6) for b in range(a + 1)])
+    assert np.array_equal(vis[0, 0], tri)
+
+
+# ---------------------------------------------------------------------------
+# P3 Parseval, P6 Hermitian/auto invariants, numpy matmul cross-check
+# ---------------------------------------------------------------------------
+def test_parseval(orc):
+    L, T = 128, 20
+    v = rand_volts(6, L * T * 2, seed=5)
+    vis = orc.fx_correlate(v, L, T)
+    for j in range(2):
+        for n in range(6):
+            lhs = vis[j, :, n * (n + 1) // 2 + n].real.sum()
+            seg = v[n, j * T * L:(j + 1) * T * L].astype(np.int64)
+            rhs = L * int((seg ** 2).sum())
+            assert abs(lhs - rhs) <= 1e-12 * rhs
+
+
+def test_hermitian_and_autos(orc):
+    L, T = 16, 8
+    v = rand_volts(5, L * T, seed=9)
+    spec = orc.channelise(v, L)
+    full = orc.correlate_full(spec, T)
+    packed = orc.correlate(spec, T)
+    n = 5
+    for a in range(n):
+        # bitwise conjugate symmetry (same summation order)
+        for b in range(n):
+            assert full[0, :, b, a].real.tobytes() == full[0, :, a, b].real.tobytes()
+            assert np.array_equal(full[0, :, b, a].imag, -full[0, :, a, b].imag)
+        assert np.all(full[0, :, a, a].imag == 0)
+        assert np.all(full[0, :, a, a].real >= 0)
+        for b in range(a + 1):
+            assert np.array_equal(packed[0, :, a * (a + 1) // 2 + b], full[0, :, a, b])
+
+
+def test_correlate_matches_numpy_matmul(orc):
+    L, T, n = 32, 10, 7
+    v = rand_volts(n, L * T, seed=12)
+    spec = orc.channelise(v, L)
+    vis = orc.correlate(spec, T, threads=3)
+    for c in range(L):
+        X = spec[:, c, :].T                  # [n][T]
+        full = X @ X.conj().T
+        tri = np.array([full[a, b] for a in range(n) for b in range(a + 1)])
+        assert np.max(np.abs(vis[0, c] - tri)) <= 1e-10 * np.max(np.abs(tri))
+
+
+def test_threads_do_not_change_results(orc):
+    L, T, n = 64, 6, 6
+    v = rand_volts(n, L * T * 2, seed=13)
+    spec = orc.channelise(v, L)
+    assert np.array_equal(orc.correlate(spec, T, 1), orc.correlate(spec, T, 5))
+
+
+# ---------------------------------------------------------------------------
+# P4 closed-form tones (the method of Sec. 3.1: phase-rotated tones)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [4, 32, 128])
+@pytest.mark.parametrize("quarter", [0, 1, 2, 3])
+def test_tone_closed_form(orc, L, quarter):
+    k0 = quarter * L // 4
+    phases = [0, 1, 2, 3, 1, 0]
+    T = 7
+    v = synth.tone_volts(6, L * T, L, k0, 11, phases)
+    vis = orc.fx_correlate(v, L, T)
+    assert tone_channel_ok(vis, L, k0, T, 11, phases)
+
+
+# ---------------------------------------------------------------------------
+# P5 point source with seeded delays: closed-form visibility phase
+# ---------------------------------------------------------------------------
+def test_point_source_phase(orc):
+    L, T, n, A, k0 = 128, 2000, 8, 2.0, 17
+    seed = synth.MWAX_SEED + 1
+    v = synth.gaussian_volts(n, L * T, sigma=8.0, seed=seed, sources=[synth.Source(A, k0)], L=L)
+    vis = orc.fx_correlate(v, L, T, threads=4)
+    taus = synth.source_delays(n, seed)
+    nu = synth.NU_C + k0 * synth.F_S / L
+    c0 = (k0 + L // 2) % L
+    assert point_source_ok(vis, c0, taus, nu, T, L, A, 2 * (64 + 1 / 12))
+
+
+# ---------------------------------------------------------------------------
+# P7 noise statistics of rounded Gaussian voltages (sigma = 8)
+# ---------------------------------------------------------------------------
+def test_noise_statistics(orc):
+    L, T, n = 128, 400, 6
+    v = synth.gaussian_volts(n, L * T, sigma=8.0, seed=synth.MWAX_SEED)
+    vis = orc.fx_correlate(v, L, T, threads=4)
+    var_c = 2 * (64 + 1 / 12)             # per complex sample, incl. rounding noise
+    vX = L * var_c
+    autos = np.array([vis[0, :, a * (a + 1) // 2 + a].real for a in range(n)])
+    ratio = autos.mean() / (vX * T)
+    assert abs(ratio - 1) < 5 / math.sqrt(T * L * n)
+    cross = np.concatenate([vis[0, :, a * (a + 1) // 2 + b] for a in range(n) for b in range(a)])
+    z = np.concatenate([cross.real, cross.imag]) / (vX * math.sqrt(T / 2))
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs((z ** 2).mean() - 1) < 5 * math.sqrt(2 / z.size)
+
+
+# ---------------------------------------------------------------------------
+# int64 X step, requantiser, calibration, fp16 rounding, tile-baseline view
+# ---------------------------------------------------------------------------
+def test_correlate_i64_brute(orc):
+    q = rng(3).integers(-127, 128, size=(9, 4, 3, 2)).astype(np.int8)
+    vis = orc.correlate_i64(q, 3)
+    for j in range(3):
+        for c in range(4):
+            for a in range(3):
+                for b in range(a + 1):
+                    sr = si = 0
+                    for m in range(3 * j, 3 * j + 3):
+                        r1, i1 = int(q[m, c, a, 0]), int(q[m, c, a, 1])
+                        r2, i2 = int(q[m, c, b, 0]), int(q[m, c, b, 1])
+                        sr += r1 * r2 + i1 * i2
+                        si += i1 * r2 - r1 * i2
+                    assert tuple(vis[j, c, a * (a + 1) // 2 + b]) == (sr, si)
+
+
+def test_correlate_i64_exceeds_int32(orc):
+    M = 100_000
+    q = np.empty((M, 1, 2, 2), np.int8)
+    q[:, 0, 0] = (127, -127)
+    q[:, 0, 1] = (-127, 127)
+    vis = orc.correlate_i64(q, M)
+    assert tuple(vis[0, 0, 0]) == (2 * 127 * 127 * M, 0)
+    # x0 conj(x1) with x0 = 127(1 - i), x1 = -127(1 - i): re = -2*127^2, im = 0
+    assert tuple(vis[0, 0, 1]) == (-2 * 127 * 127 * M, 0)
+    assert tuple(vis[0, 0, 2]) == (2 * 127 * 127 * M, 0)
+    assert vis.max() > 2 ** 31
+
+
+def test_requantise_rule(orc):
+    vals = np.array([2.5, 3.5, -2.5, -3.5, 0.5, -0.5, 1.49999, 126.6, 127.5, 300.0, -300.0,
+                     -127.5, -128.0, 0.0], np.float64)
+    spec = (vals + 1j * vals[::-1]).reshape(1, 1, -1)
+    q = orc.requantise(spec, np.array([1.0], np.float32))
+    expect_re = np.clip(np.rint(vals), -127, 127)           # numpy rint: ties to even
+    expect_im = np.clip(np.rint(vals[::-1]), -127, 127)
+    assert np.array_equal(q[0, 0, :, 0], expect_re.astype(np.int8))
+    assert np.array_equal(q[0, 0, :, 1], expect_im.astype(np.int8))
+    assert q.min() == -127
+    # per-channel scale applies per channel
+    spec = np.array([[[10 + 10j], [10 + 10j]]])
+    q = orc.requantise(spec, np.array([0.5, 0.25], np.float32))
+    assert q[0, 0, 0].tolist() == [5, 5] and q[0, 1, 0].tolist() == [2, 2]   # 2.5 -> 2
+
+
+def test_calibrate_rule(orc):
+    spec = np.zeros((3, 2, 4), complex)
+    spec[:, 0, :] = 3 + 4j          # |x|^2 / 2 = 12.5 everywhere
+    sig2, s, inv = orc.calibrate(spec)
+    assert sig2[0] == 12.5 and sig2[1] == 0.0
+    assert s[0] == np.float32(5 * math.sqrt(12.5) / 127)
+    assert inv[0] == np.float32(127 / (5 * math.sqrt(12.5)))
+    assert s[1] == 1.0 and inv[1] == 1.0
+
+
+def test_calibrate_white_noise(orc):
+    L = 64
+    v = synth.gaussian_volts(8, L * 200, sigma=8.0, seed=42)
+    sig2, _, _ = orc.calibrate(orc.channelise(v, L))
+    # E|X|^2 = L * 2 * 64.083, so sigma^2 per component = L * 64.083
+    assert abs(sig2.mean() / (L * (64 + 1 / 12)) - 1) < 0.02
+
+
+def test_round_fp16_matches_numpy(orc):
+    r = rng(21)
+    x = np.concatenate([
+        r.normal(size=2000) * 1000, r.normal(size=500) * 1e-5, r.normal(size=200) * 6e4,
+        np.array([0.0, -0.0, 65504.0, 65519.9, 65520.0, -70000.0, 2.0 ** -24, 2.0 ** -25,
+                  3 * 2.0 ** -26, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, 2049.0, 2051.0]),
+    ])
+    y = orc.round_fp16(x)
+    ref = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(y, ref)
+    assert np.array_equal(orc.round_fp16(x, 0.25), (x * 0.25).astype(np.float16).astype(np.float64))
+
+
+def test_pack_tilebl(orc):
+    n_tiles, L = 3, 2
+    n = 2 * n_tiles
+    P = n * (n + 1) // 2
+    vis = (np.arange(L * P) + 1j * (1000 + np.arange(L * P))).reshape(L, P)
+    out = orc.pack_tilebl(vis, n_tiles)
+    assert out.shape == (6, L, 4)
+
+    def V(c, r, s):
+        return vis[c, r * (r + 1) // 2 + s] if r >= s else np.conj(vis[c, s * (s + 1) // 2 + r])
+
+    for a in range(n_tiles):
+        for b in range(a + 1):
+            bl = a * (a + 1) // 2 + b
+            for c in range(L):
+                assert out[bl, c, 0] == V(c, 2 * a, 2 * b)          # XX
+                assert out[bl, c, 1] == V(c, 2 * a, 2 * b + 1)      # XY
+                assert out[bl, c, 2] == V(c, 2 * a + 1, 2 * b)      # YX
+                assert out[bl, c, 3] == V(c, 2 * a + 1, 2 * b + 1)  # YY
+    # auto-tile XY is the conjugate of YX
+    assert out[0, 0, 1] == np.conj(out[0, 0, 2])
+
+
+# ---------------------------------------------------------------------------
+# The pins notice planted mistakes
+# ---------------------------------------------------------------------------
+def test_pins_catch_conjugation_error(orc):
+    L, T, n, A, k0 = 128, 2000, 6, 2.0, 17
+    seed = synth.MWAX_SEED + 1
+    v = synth.gaussian_volts(n, L * T, seed=seed, sources=[synth.Source(A, k0)], L=L)
+    vis = orc.fx_correlate(v, L, T, threads=4)
+    taus = synth.source_delays(n, seed)
+    nu = synth.NU_C + k0 * synth.F_S / L
+    c0 = (k0 + L // 2) % L
+    args = (c0, taus, nu, T, L, A, 2 * (64 + 1 / 12))
+    assert point_source_ok(vis, *args)
+    assert not point_source_ok(np.conj(vis), *args)          # x1* x2 instead of x1 x2*
+
+
+def test_pins_catch_missing_fftshift_and_wrong_sign(orc):
+    L, T = 32, 5
+    phases = [0, 1, 3]
+    v = synth.tone_volts(3, L * T, L, L // 4, 9, phases)
+    vis = orc.fx_correlate(v, L, T)
+    assert tone_channel_ok(vis, L, L // 4, T, 9, phases)
+    assert not tone_channel_ok(np.roll(vis, L // 2, axis=1), L, L // 4, T, 9, phases)
+    # inverse-sign transform puts the tone at -k0: channel mirrored about DC
+    mirrored = np.concatenate([vis[:, :1], vis[:, :0:-1]], axis=1)
+    assert not tone_channel_ok(mirrored, L, L // 4, T, 9, phases)
+
+
+def test_pins_catch_dropped_term(orc):
+    n_in, L, M, T = 3, 4, 4, 2
+    v = rand_volts(n_in, L * M, seed=77)
+    vis = orc.fx_correlate(v, L, T)
+    V = brute_force_vis(v, L, T)
+    assert check_brute_force(vis, V, 1e-9)
+    # drop the i1*i2 term of the real part (equivalent: keep only r1 r2)
+    spec = orc.channelise(v, L)
+    bad = np.zeros_like(vis)
+    for j in range(M // T):
+        for a in range(n_in):
+            for b in range(a + 1):
+                s = spec[j * T:(j + 1) * T]
+                bad[j, :, a * (a + 1) // 2 + b] = (
+                    (s[:, :, a].real * s[:, :, b].real).sum(0)
+                    + 1j * (s[:, :, a].imag * s[:, :, b].real - s[:, :, a].real * s[:, :, b].imag).sum(0))
+    assert not check_brute_force(bad, V, 1e-9)
+    # transposed operand (x2 x1*) breaks the brute-force comparison as well
+    assert not check_brute_force(np.conj(vis), V, 1e-9)
