@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the FX correlation hot path on one MI355X.
+
+Workload (one step = one pass of the whole hot path over one 8 s block):
+256 tiles x 2 pols = 512 inputs, one 1.28 MHz coarse channel, 8 s of complex
+int8 voltages (10.24 M samples per input, Gaussian sigma = 8 plus three point
+sources, seeded, generated on the device), 128-point FFT (10 kHz channels),
+one 8 s integration.  Per step: channelise (per-integration int8 scale
+calibration, FFT, requantise, transpose) -> correlate (int8 MFMA X-engine) ->
+integrate (pack the 131,328-pair lower triangle x 128 channels).
+
+Printed: one JSON line with the X-engine CMAC/s of the whole step (value), the
+real-time factor, the dominant kernel's roofline fraction (HIP-event timing on
+the plan's stream), the FP16 / FP32-plain X-engines on the same block, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_gbs": 8000.0,
+    "int8_tops": 5000.0,
+    "fp16_tflops": 2500.0,
+    "fp32_vector_tflops": 157.3,
+}
+N_TILES, L, SECONDS, F_S = 256, 128, 8.0, 1.28e6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+KERNEL_SOURCES = {
+    "xengine": os.path.join(ROOT, "paper_2303_11557_amd", "csrc", "xengine.hip"),
+    "fengine": os.path.join(ROOT, "paper_2303_11557_amd", "csrc", "fengine.hip"),
+}
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--xprec", default="int8", choices=["int8", "fp16", "fp32"])
+    ap.add_argument("--variants", default="fp16,fp32",
+                    help="other X-engine precisions to time on the same block ('none' to skip)")
+    ap.add_argument("--variant-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(coarse channels shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+    from paper_2303_11557_amd.mwax import Plan, make_config
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    S = int(SECONDS * F_S)
+    n_in = 2 * N_TILES
+    T = S // L
+    P = n_in * (n_in + 1) // 2
+    cmac_per_step = P * S                   # distinct Hermitian entries x samples
+    sources = [synth.Source(2.0, -37), synth.Source(3.0, 5), synth.Source(4.0, 41)]
+    volts = torch.empty((n_in, S, 2), dtype=torch.int8, device="cuda")
+    synth.device_volts(volts, seed=synth.MWAX_SEED + 2, sources=sources, L=L)
+    torch.cuda.synchronize()
+
+    def run_variant(prec, steps, warmup):
+        with Plan(make_config(N_TILES, L=L, T=T, xprec=prec, max_samples=S)) as p:
+            out = torch.empty((1, L, P), dtype=torch.complex64, device="cuda")
+
+            def step():
+                p.channelise(volts)
+                p.correlate()
+                p.integrate(1, out=out)
+
+            for _ in range(warmup):
+                step()
+            p.sync()
+            p.set_timing(True)
+            for fam in (0, 1, 2):
+                p.kernel_time(fam)               # clear
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            p.sync()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fam = {name: p.kernel_time(i) for i, name in enumerate(("fengine", "xengine", "pack"))}
+            p.set_timing(False)
+        ms = (t1 - t0) * 1e3 / steps
+        return ms, fam, out
+
+    ms, fam, out = run_variant(args.xprec, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    value = cmac_per_step / (ms / 1e3)
+
+    # ---- roofline of the kernels (algorithmic work per launch / event-timed duration)
+    f_ms, f_n = fam["fengine"]
+    x_ms, x_n = fam["xengine"]
+    p_ms, p_n = fam["pack"]
+    b_out = {"int8": 2, "fp16": 4, "fp32": 8}[args.xprec]
+    x_peak = {"int8": PEAK["int8_tops"], "fp16": PEAK["fp16_tflops"], "fp32": PEAK["fp32_vector_tflops"]}[args.xprec]
+    x_ops_launch = 8.0 * cmac_per_step * args.steps / max(x_n, 1)
+    x_avg_ms = x_ms / max(x_n, 1)
+    x_achieved = x_ops_launch / (x_avg_ms / 1e3) / 1e12
+    # F-engine: int8 in + channelised out per sample of every input (main pass; the
+    # calibration pass over the first 1024 spectra of each integration is counted in
+    # the F-engine time, not in its bytes)
+    f_bytes_step = n_in * S * (2 + b_out)
+    f_gbs = f_bytes_step * args.steps / (f_ms / 1e3) / 1e9 if f_ms > 0 else 0.0
+
+    traffic = None
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get(f"xengine_{args.xprec}")
+        if ent and ent.get("source_sha") == source_hash(KERNEL_SOURCES["xengine"]):
+            traffic = ent["hbm_bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+
+    roof_x = {"kernel": f"xengine_{args.xprec}", "bound": "mfma" if args.xprec != "fp32" else "alu",
+              "achieved": round(x_achieved, 2), "peak": x_peak, "unit": "TFLOP/s",
+              "frac": round(x_achieved / x_peak, 4), "traffic": traffic,
+              "avg_launch_ms": round(x_avg_ms, 4), "launches": x_n,
+              "ops_per_launch": x_ops_launch}
+    roof_f = {"kernel": f"fengine_{args.xprec}", "bound": "hbm", "achieved": round(f_gbs, 1),
+              "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(f_gbs / PEAK["hbm_gbs"], 4),
+              "traffic": None, "time_ms_per_step": round(f_ms / args.steps, 4),
+              "bytes_per_step": f_bytes_step}
+    dominant, other = (roof_x, roof_f) if x_ms >= f_ms else (roof_f, roof_x)
+
+    # ---- other X-engine precisions on the same block
+    variants = {}
+    if args.variants != "none":
+        for prec in [v for v in args.variants.split(",") if v and v != args.xprec]:
+            vms, vfam, _ = run_variant(prec, args.variant_steps, 1)
+            vx_ms, vx_n = vfam["xengine"]
+            vpeak = {"int8": PEAK["int8_tops"], "fp16": PEAK["fp16_tflops"],
+                     "fp32": PEAK["fp32_vector_tflops"]}[prec]
+            vach = 8.0 * cmac_per_step * args.variant_steps / (vx_ms / 1e3) / 1e12
+            variants[prec] = {
+                "ms_per_step": round(vms, 3), "cmac_per_s": cmac_per_step / (vms / 1e3),
+                "xengine_ms_per_step": round(vx_ms / args.variant_steps, 3),
+                "xengine_tflops": round(vach, 2), "xengine_peak": vpeak,
+                "xengine_frac": round(vach / vpeak, 4), "rtf_per_channel": round(SECONDS / (vms / 1e3), 2),
+            }
+            torch.cuda.empty_cache()
+        if "fp32" in variants:
+            variants["speedup_vs_fp32_plain"] = round(variants["fp32"]["ms_per_step"] / ms, 2)
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same block
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        max_spec = 2048
+        v_host = volts[:, : max_spec * L].cpu().numpy()
+
+        def oracle_rate(n_spec):
+            t0 = time.perf_counter()
+            spec = oracle.channelise(v_host, L, nm=n_spec)
+            oracle.correlate(spec, n_spec, threads=threads)
+            return time.perf_counter() - t0
+
+        probe = 2
+        dt = oracle_rate(probe)
+        n_spec = int(max(probe, min(max_spec, probe * args.cpu_seconds / max(dt, 1e-3))))
+        dt = oracle_rate(n_spec)
+        cpu = {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
+                         f"({n_spec * L} samples) of the same 8 s block; FP64 FFT + packed triangle; "
+                         f"{dt:.1f} s wall"}
+
+    rtf = SECONDS / (ms / 1e3)
+    line = {
+        "metric": "X-engine CMAC/s & real-time factor at 256 tiles: int8/FP16 MFMA vs FP32 plain",
+        "value": value,
+        "unit": "CMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.xprec,
+        "data": "synthetic",
+        "config": {
+            "workload": "256 tiles x 2 pols, 1 coarse channel, 8 s (10.24 M samples) complex int8 "
+                        "Gaussian sigma=8 + 3 point sources, 128-pt FFT, one 8 s integration, "
+                        f"{args.xprec} X-engine",
+            "n_inputs": n_in, "samples": S, "fft_len": L, "spectra_per_integration": T,
+            "pairs": P, "cmac_per_step": cmac_per_step,
+        },
+        "rtf_per_channel": round(rtf, 2),
+        "rtf_24_channels": round(rtf / 24.0, 2),
+        "roofline": dominant,
+        "roofline_other": other,
+        "pack_ms_per_step": round(p_ms / max(args.steps, 1), 4),
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

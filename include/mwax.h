@@ -1,0 +1,222 @@
+/*
+ * mwax.h -- C ABI of the MI355X FX correlation hot path.
+ *
+ * Implements, for one GPU, the per-coarse-channel FX engine of Morrison et al.,
+ * "MWAX: A New Correlator for the Murchison Widefield Array" (PASA 2023):
+ *   - fine channelisation by FFT of complex int8 voltage streams (Sec. 2.5,
+ *     Sec. 2.5.1), channels centre-symmetric with DC at c = L/2 (Sec. 2.6);
+ *   - the transpose to channel-major order ahead of the X-engine (Sec. 2.5.1);
+ *   - the X-engine: for every channel c and input pair n1 >= n2, autos
+ *     included, V[c][n1,n2] += sum_m X_n1[m,c] conj(X_n2[m,c]) (Sec. 2.5.2);
+ *   - time integration and output of the packed lower triangle
+ *     (Sec. 2.5.2, Sec. 2.7).
+ *
+ * Conventions used throughout:
+ *   inputs      n = 2*tile + pol (pol 0 = X, 1 = Y): the [tile][polarisation]
+ *               order of Sec. 2.5.1.  n_inputs = 2 * n_tiles.
+ *   FFT         unnormalised forward transform over contiguous, non-overlapping
+ *               frames of L samples, rectangular window.
+ *   channels    c = (k + L/2) mod L for FFT bin k; channel c is centred at
+ *               (c - L/2) * coarse_bw / L from the coarse-channel centre.
+ *   visibility  sums (not means) over the spectra of an integration.
+ *   pair index  p(n1, n2) = n1 (n1 + 1) / 2 + n2 for n1 >= n2; P = n(n+1)/2.
+ *
+ * Memory: every pointer named d_* is device memory on the plan's device; h_*
+ * is host memory.  The caller owns all buffers it passes; the plan owns its
+ * workspace (allocated by mwax_plan_create, released by mwax_plan_destroy).
+ *
+ * Asynchrony: calls enqueue work on the plan's stream and return.  Argument
+ * and call-order errors return at once and enqueue nothing.  Runtime errors
+ * seen at launch return MWAX_E_DEVICE; faults raised while kernels run are
+ * reported by the HIP runtime at the next synchronisation (mwax_sync).
+ *
+ * Threading: a plan must not be used from two threads at once.  Distinct plans
+ * are independent.  No C++ exception crosses this interface.
+ */
+#ifndef MWAX_H
+#define MWAX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mwax_plan_s *mwax_plan;
+
+typedef enum {
+    MWAX_OK = 0,
+    MWAX_E_INVAL = 1,       /* bad argument or configuration; nothing enqueued       */
+    MWAX_E_NOMEM = 2,       /* device allocation failed                               */
+    MWAX_E_DEVICE = 3,      /* HIP runtime error                                      */
+    MWAX_E_STATE = 4,       /* call out of order (see each call)                      */
+    MWAX_E_UNSUPPORTED = 5  /* a valid request this library does not implement        */
+} mwax_status;
+
+/* Arithmetic of the X-engine (precision forms beyond the paper's FP32,
+ * Sec. 2.5.1 and 2.5.2 use single precision throughout):
+ *   FP32: spectra kept in FP32, X-engine on the vector ALUs in FP32, partial
+ *         sums flushed to FP64 integrators every 2048 spectra.
+ *   FP16: spectra scaled by 2^-e, e = ceil(log2(L)/2), rounded to binary16
+ *         (ties to even); X-engine on FP16 matrix cores with FP32 accumulation,
+ *         flushed to FP64 integrators; output scaled back by 2^(2e).
+ *   INT8: spectra requantised per channel to q = clamp(rne(X * inv_s_c), -127,
+ *         127); X-engine on int8 matrix cores with int32 accumulation flushed to
+ *         int64 integrators (exact); output V = V_int * s_c^2. */
+typedef enum { MWAX_X_FP32 = 0, MWAX_X_FP16 = 1, MWAX_X_INT8 = 2 } mwax_xprec;
+
+/* Output orders of mwax_integrate:
+ *   CHAN_TRI: [integration][channel][P] complex64, packed lower triangle.
+ *   TILE_BL : [integration][baseline][channel][4] complex64, baselines a >= b
+ *             at a(a+1)/2 + b, products XX, XY, YX, YY (pol of tile a first);
+ *             the auto-tile XY is conj(YX).  Sec. 2.7 orders its output by
+ *             baseline, channel and polarisation; its exact figure is not in
+ *             the text, so this layout is not claimed to match it bit for bit. */
+typedef enum { MWAX_ORDER_CHAN_TRI = 0, MWAX_ORDER_TILE_BL = 1 } mwax_order;
+
+/* Plan configuration, following the paper's statement of the problem:
+ * N tiles x 2 polarisations (Sec. 2.5), 1.28 MHz coarse channels sampled at
+ * 1.28 Msps complex (Sec. 2.1, Sec. 2.5), a chosen fine-channel width and
+ * integration time (Table 1, Sec. 2.5.2). */
+typedef struct {
+    int32_t n_tiles;       /* 1 .. 1024                                                   */
+    int32_t n_pols;        /* must be 2                                                   */
+    double coarse_bw_hz;   /* complex sample rate == coarse bandwidth (1.28e6 for MWA)     */
+    double fine_chan_hz;   /* L = coarse_bw / fine_chan: a whole number; this library
+                              implements powers of two 1 .. 1024 (others: UNSUPPORTED)  */
+    double int_time_s;     /* T = int_time * coarse_bw / L must be an integer >= 1         */
+    int32_t xprec;         /* mwax_xprec                                                  */
+    int32_t reserved;      /* must be 0                                                   */
+    int64_t max_samples;   /* largest n_samples of one channelise call; multiple of L     */
+    uint64_t flags;        /* must be 0                                                   */
+} mwax_config;
+
+/* Quantities derived from a configuration (host arithmetic only). */
+typedef struct {
+    int32_t n_inputs;          /* 2 * n_tiles                                          */
+    int32_t fft_len;           /* L                                                    */
+    int64_t spectra_per_int;   /* T                                                    */
+    int64_t n_pairs;           /* P = n_inputs (n_inputs + 1) / 2                      */
+    int64_t n_baselines;       /* n_tiles (n_tiles + 1) / 2                            */
+    int64_t max_spectra;       /* max_samples / L                                      */
+    int32_t n_slots;           /* integrations the plan can hold on the device         */
+    int32_t group;             /* spectra per 32-byte row of the channel-major layout  */
+    int64_t vis_per_int;       /* L * P complex values per integration (CHAN_TRI)      */
+    int64_t cal_spectra;       /* spectra used to calibrate an integration's scales    */
+    uint64_t workspace_bytes;  /* device bytes a plan allocates                        */
+    double sample_time_s;      /* 1 / coarse_bw                                        */
+    double fine_chan_hz;       /* coarse_bw / L                                        */
+    double int_time_s;         /* T * L / coarse_bw                                    */
+} mwax_dims;
+
+/* Validate a configuration and derive its dimensions.  Host only: touches no
+ * GPU, so it can be called anywhere.  MWAX_E_INVAL with a message for any rule
+ * the configuration breaks (see mwax_config); MWAX_E_UNSUPPORTED for a whole
+ * FFT length that is not a power of two in 1..1024 (e.g. the 6,400-point
+ * transform of Sec. 2.5.1). */
+mwax_status mwax_plan_derive(const mwax_config *cfg, mwax_dims *out);
+
+/* Create a plan on the current HIP device.  hip_stream is a hipStream_t (NULL
+ * for the default stream) on which every later call of the plan enqueues.
+ * Allocates the workspace (channel-major buffer for max_samples, integrators,
+ * scales, twiddles) and generates the FFT twiddles on the device in FP64.
+ * Errors: MWAX_E_INVAL (configuration), MWAX_E_NOMEM, MWAX_E_DEVICE. */
+mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out);
+
+/* Release the plan and its workspace (waits for its stream first).  NULL is
+ * accepted and ignored. */
+mwax_status mwax_plan_destroy(mwax_plan p);
+
+/* The plan's dimensions (see mwax_dims). */
+mwax_status mwax_plan_get_dims(mwax_plan p, mwax_dims *out);
+
+/* F-engine (Sec. 2.5.1): channelise n_samples samples of every input.
+ *   d_volts   : int8 [n_inputs][ld_samples][2] (re, im) complex samples; must be
+ *               16-byte aligned, ld_samples a multiple of 8 and >= n_samples.
+ *   n_samples : > 0, a multiple of L, <= max_samples.
+ * The samples continue the stream of earlier calls: integration boundaries
+ * fall every T spectra of the concatenated stream.  Transforms every frame,
+ * requantises (INT8: with the scales of the integration each spectrum belongs
+ * to; FP16: to binary16) and writes the channel-major buffer.  For INT8 plans
+ * in automatic-scale mode, each integration that begins in this call first
+ * has its per-channel scales calibrated from its first cal_spectra spectra
+ * (or as many as this call holds): sigma_c^2 = mean of (re^2 + im^2)/2 over
+ * inputs and those spectra, s_c = 5 sigma_c / 127, inv_s_c = 127 / (5 sigma_c);
+ * a channel with zero power gets s_c = 1.
+ * Errors: MWAX_E_INVAL (arguments); MWAX_E_STATE if the previous channelised
+ * block has not been correlated, or if an integration this call would start
+ * needs a device slot still held by a completed integration that
+ * mwax_integrate has not emitted. */
+mwax_status mwax_channelise(mwax_plan p, const int8_t *d_volts, int64_t n_samples,
+                            int64_t ld_samples);
+
+/* Load already channelised data in place of mwax_channelise, in the X-engine
+ * input order of Sec. 2.5.1, [time][channel][tile][pol]:
+ *   d_chan: [n_spectra][L][n_inputs][2] of the plan's element type: int8
+ *           (values in -127..127; -128 is clamped to -127), binary16 bits
+ *           (uint16), or float32.  INT8 plans apply their fixed scales (see
+ *           mwax_set_scales) or 1.0 at output; FP16 values are taken as
+ *           spectra times 2^-e like those mwax_channelise stores.
+ * Same stream position and state rules as mwax_channelise. */
+mwax_status mwax_load_channelised(mwax_plan p, const void *d_chan, int64_t n_spectra);
+
+/* Copy out the channelised block last produced by mwax_channelise or
+ * mwax_load_channelised, in the [time][channel][input][2] order above and the
+ * plan's element type, spectra in stream order.  Needs d_out to hold
+ * n_spectra * L * n_inputs * 2 elements with n_spectra <= max_spectra;
+ * writes the count to *n_spectra.  MWAX_E_STATE if nothing was channelised. */
+mwax_status mwax_read_channelised(mwax_plan p, void *d_out, int64_t max_spectra,
+                                  int64_t *n_spectra);
+
+/* X-engine (Sec. 2.5.2): accumulate the last channelised block into the
+ * device integrators.  MWAX_E_STATE if there is no fresh channelised block. */
+mwax_status mwax_correlate(mwax_plan p);
+
+/* Emit up to max_ints completed integrations, oldest first, into d_vis
+ * (complex64 in the given mwax_order; CHAN_TRI needs max_ints * L * P values,
+ * TILE_BL max_ints * n_baselines * L * 4), then clear their integrators.
+ * *n_emitted receives the count (0 if none is complete).  Integrations still
+ * in progress are kept. */
+mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *n_emitted,
+                           int32_t order);
+
+/* INT8 plans only: like mwax_integrate in CHAN_TRI order but emits the exact
+ * int64 sums, d_vis = [max_ints][L][P][2] int64 (re, im), and, if d_scales is
+ * not NULL, the per-channel scales s_c used, [max_ints][L] float32.
+ * MWAX_E_UNSUPPORTED for other precisions. */
+mwax_status mwax_integrate_raw_i64(mwax_plan p, int64_t *d_vis, float *d_scales,
+                                   int32_t max_ints, int32_t *n_emitted);
+
+/* INT8 plans: fix the per-channel scales s_c (h_scales: [L] host floats > 0)
+ * for every integration that starts after this call; inv_s_c = 1/s_c in FP32.
+ * mwax_auto_scales returns to per-integration calibration.  Both return
+ * MWAX_E_STATE while an integration is partly accumulated and
+ * MWAX_E_UNSUPPORTED for other precisions. */
+mwax_status mwax_set_scales(mwax_plan p, const float *h_scales);
+mwax_status mwax_auto_scales(mwax_plan p);
+
+/* Discard every integration in progress or not yet emitted and any pending
+ * channelised block; the stream position returns to zero. */
+mwax_status mwax_reset(mwax_plan p);
+
+/* Wait for the plan's stream.  MWAX_E_DEVICE if the runtime reports an error. */
+mwax_status mwax_sync(mwax_plan p);
+
+/* Kernel timing for measurement.  When enabled, the plan records HIP events on
+ * its stream around each launch of the F-engine, X-engine and pack kernels.
+ * mwax_kernel_time synchronises the stream and returns, for a kernel family
+ * (0 = F-engine incl. calibration, 1 = X-engine, 2 = pack), the summed
+ * duration in milliseconds and the launch count since the last read, then
+ * clears them. */
+mwax_status mwax_set_timing(mwax_plan p, int32_t enable);
+mwax_status mwax_kernel_time(mwax_plan p, int32_t family, double *total_ms, int64_t *launches);
+
+/* Message for the last error of the calling thread (empty if none). */
+const char *mwax_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MWAX_H */

@@ -1,0 +1,110 @@
+// Internal declarations shared by the runtime and the kernel files of libmwax.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mwax.h"
+
+namespace mwax {
+
+// Every row of the channel-major buffer is 32 bytes: G spectra of one input in
+// one channel, real parts first then imaginary parts (int8: 16 + 16 bytes,
+// binary16: 8 + 8 halves, float32: 4 + 4 floats).  This is the operand order
+// the matrix cores read: one 16-byte half row per lane.
+constexpr int kRowBytes = 32;
+
+inline int group_of(int xprec) {
+    return xprec == MWAX_X_INT8 ? 16 : (xprec == MWAX_X_FP16 ? 8 : 4);
+}
+
+// Binary16 scaling exponent e = ceil(log2(L) / 2): |X| 2^-e <= 127 sqrt(2 L) 2^-e
+// stays far below 65504 for every supported L.
+inline int fp16_exponent(int L) {
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    return (lg + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// F-engine
+// ---------------------------------------------------------------------------
+struct FArgs {
+    const int8_t *volts;    // [N_in][ld][2]
+    int64_t ld;             // samples between input rows
+    int64_t frame0;         // first source frame (call-local) of the segment
+    int64_t nframes;        // frames in the segment
+    uint8_t *chan;          // channel-major buffer [L][NG][N_in][32 B]
+    int64_t NG;             // row groups per channel in the buffer
+    int64_t grp0;           // first destination group of the segment
+    int32_t n_in;           // inputs
+    int32_t R;              // inputs per workgroup
+    int32_t ngrp;           // destination groups of the segment (or calibration groups)
+    int32_t stats_mode;     // 1: accumulate per-channel power instead of writing
+    const float2 *tw;       // W_L^k = exp(-2 pi i k / L), k < L
+    const float *inv_s;     // [L] INT8 inverse scales of the segment's integration
+    float half_scale;       // 2^-e for FP16
+    double *stats;          // stats mode: [n_workgroups][L] partial power sums
+};
+
+constexpr int kStatsMaxWG = 1024;   // calibration partial rows per launch (max)
+int fengine_lds_bytes(int L, int xprec, int R, bool stats);
+int fengine_grid(int n_in, int R, int ngrp, bool stats);
+constexpr int kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+int fengine_pick_R(int L, int xprec, int n_in, int lds_limit);
+hipError_t launch_fengine(int L, int xprec, const FArgs &a, hipStream_t s);
+hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s);
+// stats: [nwg][L] partial sums -> scales [2][L] (s, inv_s) for one slot
+hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count, float *scales,
+                               hipStream_t s);
+hipError_t launch_copy_scales(const float *src, float *dst, int L, hipStream_t s);
+
+// Canonical [M][L][N_in][2] <-> internal layout, one segment at a time.
+struct RepackArgs {
+    void *canon;            // [M][L][N_in][2] elements
+    int64_t m0;             // first canonical spectrum of the segment
+    int64_t nframes;        // spectra in the segment
+    uint8_t *chan;
+    int64_t NG, grp0;
+    int32_t n_in, L, G, esize;  // elements per row half = G; element bytes
+    int32_t to_internal;    // 1: canon -> chan (load), 0: chan -> canon (read)
+};
+hipError_t launch_repack(const RepackArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// X-engine
+// ---------------------------------------------------------------------------
+struct XArgs {
+    const uint8_t *chan;    // [L][NG][N_in][32 B]
+    int64_t NG;
+    int64_t grp0;           // first group of the segment
+    int32_t ngrp;           // groups in the segment
+    int32_t n_in;
+    int32_t L;
+    int32_t ntiles;         // lower-triangle tiles per channel
+    int32_t tile;           // tile edge (rows)
+    void *integ;            // this slot's integrators [L][P][2] (int64 or double)
+    int64_t P;
+};
+hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s);
+int xengine_tile(int xprec);
+
+// ---------------------------------------------------------------------------
+// Integrate / pack
+// ---------------------------------------------------------------------------
+struct PackArgs {
+    void *integ;            // slot integrators [L][P][2], cleared after reading
+    int32_t is_int;         // int64 (1) or double (0) integrators
+    const float *scales;    // INT8: s_c [L]; else NULL
+    double post;            // FP16/FP32: multiply by this (2^(2e) or 1)
+    void *out;              // complex64 or int64 output of this integration
+    float *scales_out;      // raw mode: copy of s_c, may be NULL
+    int32_t order;          // mwax_order; 2 = raw int64
+    int32_t L;
+    int32_t n_in;
+    int64_t P;
+};
+hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace mwax

@@ -1,0 +1,116 @@
+// Integration output (Morrison et al. 2023, Sec. 2.5.2 and 2.7): turn one
+// completed integration's device integrators into the output visibilities and
+// clear them for reuse.  Done on the device rather than on the host CPU.
+//
+//   CHAN_TRI: out[c][p] = complex64(scale(V[c][p])), p = n1(n1+1)/2 + n2
+//   TILE_BL : out[bl][c][pp] for tile baselines a >= b (bl = a(a+1)/2 + b) and
+//             products pp = 2 p1 + p2 in the order XX, XY, YX, YY, taken from
+//             input pair (2a+p1, 2b+p2); above the diagonal (auto-tile XY) the
+//             conjugate of the mirrored entry.
+//   raw     : out[c][p] = the exact int64 sums (INT8 integrators).
+// scale: INT8 V_int * s_c * s_c (computed in FP64), FP16 and FP32 V * post.
+#include "mwax_internal.h"
+
+namespace mwax {
+namespace {
+
+__device__ __forceinline__ float2 scaled(const PackArgs &a, int64_t idx, int c) {
+    if (a.is_int) {
+        const longlong2 v = reinterpret_cast<const longlong2 *>(a.integ)[idx];
+        const double s = (double)a.scales[c];
+        return make_float2((float)((double)v.x * s * s), (float)((double)v.y * s * s));
+    }
+    const double2 v = reinterpret_cast<const double2 *>(a.integ)[idx];
+    return make_float2((float)(v.x * a.post), (float)(v.y * a.post));
+}
+
+__global__ void pack_tri_kernel(PackArgs a) {
+    const int64_t total = (int64_t)a.L * a.P;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t / a.P);
+        if (a.order == 2) {
+            longlong2 *src = reinterpret_cast<longlong2 *>(a.integ) + t;
+            reinterpret_cast<longlong2 *>(a.out)[t] = *src;
+            *src = make_longlong2(0, 0);
+        } else {
+            reinterpret_cast<float2 *>(a.out)[t] = scaled(a, t, c);
+            if (a.is_int) reinterpret_cast<longlong2 *>(a.integ)[t] = make_longlong2(0, 0);
+            else reinterpret_cast<double2 *>(a.integ)[t] = make_double2(0.0, 0.0);
+        }
+    }
+    if (a.scales_out) {
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.L;
+             c += (int64_t)gridDim.x * blockDim.x)
+            a.scales_out[c] = a.scales[c];
+    }
+}
+
+__device__ __forceinline__ int64_t tri_row(int64_t t) {
+    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    return i;
+}
+
+// gather pass of the tile-baseline order (integrators cleared afterwards)
+__global__ void pack_tilebl_kernel(PackArgs a) {
+    const int64_t nt = a.n_in / 2;
+    const int64_t total = nt * (nt + 1) / 2 * a.L * 4;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int pp = (int)(t & 3);
+        const int64_t rest = t >> 2;
+        const int c = (int)(rest % a.L);
+        const int64_t bl = rest / a.L;
+        const int64_t ta = tri_row(bl);
+        const int64_t tb = bl - ta * (ta + 1) / 2;
+        const int64_t r = 2 * ta + (pp >> 1), s = 2 * tb + (pp & 1);
+        float2 v;
+        if (r >= s) {
+            v = scaled(a, (int64_t)c * a.P + r * (r + 1) / 2 + s, c);
+        } else {
+            v = scaled(a, (int64_t)c * a.P + s * (s + 1) / 2 + r, c);
+            v.y = -v.y;
+        }
+        reinterpret_cast<float2 *>(a.out)[t] = v;
+    }
+}
+
+__global__ void fill_zero_kernel(uint4 *p, int64_t n16) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16;
+         t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = make_uint4(0, 0, 0, 0);
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if ((bytes & 15) || ((uintptr_t)p & 15)) return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n16)), dim3(256), 0, s, (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
+    if (a.order == MWAX_ORDER_TILE_BL) {
+        const int64_t nt = a.n_in / 2;
+        const int64_t total = nt * (nt + 1) / 2 * a.L * 4;
+        hipLaunchKernelGGL(pack_tilebl_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
+    }
+    hipLaunchKernelGGL(pack_tri_kernel, dim3(grid_for((int64_t)a.L * a.P)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mwax

@@ -1,0 +1,638 @@
+// Host runtime of libmwax: plan derivation, workspace, stream position and
+// integration bookkeeping, kernel launches, error reporting.  Implements the C
+// ABI declared in mwax.h.
+//
+// Stream model (Sec. 2.5.2: integrations are whole numbers of spectra of a
+// continuous stream).  The voltage stream is cut into spectra of L samples;
+// integration j covers stream spectra [jT, (j+1)T).  A channelise call covering
+// stream spectra [g, g+M) is split into segments at integration boundaries;
+// each segment is laid out in the channel-major buffer from a fresh row group,
+// so no row group mixes two integrations.  Integration j accumulates in device
+// slot j mod n_slots until mwax_integrate emits it.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mwax_internal.h"
+
+using namespace mwax;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mwax_status fail(mwax_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+mwax_status ok() {
+    g_last_error.clear();
+    return MWAX_OK;
+}
+
+mwax_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? MWAX_E_NOMEM : MWAX_E_DEVICE,
+                "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kCalSamples = 131072;   // calibration window: 0.1024 s at 1.28 Msps
+
+struct Segment {
+    int64_t j;        // integration index
+    int slot;         // device slot
+    int64_t frame0;   // first spectrum of the segment within the call
+    int64_t nframes;  // spectra in the segment
+    int64_t grp0;     // first row group in the channel-major buffer
+    int64_t ngrp;     // row groups
+    int64_t local0;   // offset of the first spectrum within integration j
+};
+
+}  // namespace
+
+struct mwax_plan_s {
+    mwax_config cfg{};
+    mwax_dims d{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int L = 0, G = 0, n_in = 0, xprec = 0, R = 1, ntiles = 0;
+    int64_t T = 0, P = 0;
+
+    uint8_t *chan = nullptr;
+    int64_t NG = 0;
+    void *integ = nullptr;
+    size_t slot_bytes = 0;
+    int nslots = 0;
+    float *scales = nullptr;        // [nslots][2][L] (s, inv_s)
+    float *fixed = nullptr;         // [2][L] user scales
+    float *ones = nullptr;          // [2][L] = 1
+    float2 *tw = nullptr;
+    double *stats = nullptr;        // [kStatsMaxWG][L]
+
+    int64_t g_chan = 0;             // stream spectra channelised (incl. the pending block)
+    bool pending = false;           // a channelised block awaits mwax_correlate
+    bool have_block = false;        // the buffer holds a block (for read-back)
+    int64_t block_spectra = 0;
+    std::vector<Segment> segs;
+    std::vector<int64_t> slot_owner, slot_count;
+    int64_t next_emit = 0;
+    bool fixed_mode = false;
+
+    bool timing = false;
+    struct Ev { hipEvent_t a, b; int fam; };
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> pool;
+    double t_ms[3] = {0, 0, 0};
+    int64_t t_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+hipEvent_t get_event(mwax_plan p) {
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Wraps a launch with timing events when timing is on.
+template <class F>
+hipError_t timed(mwax_plan p, int fam, F &&launch) {
+    if (!p->timing) return launch();
+    hipEvent_t a = get_event(p), b = get_event(p);
+    if (!a || !b) return hipErrorOutOfMemory;
+    (void)hipEventRecord(a, p->stream);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, p->stream);
+    p->events.push_back({a, b, fam});
+    return e;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+mwax_status derive(const mwax_config *cfg, mwax_dims *o) {
+    if (!cfg || !o) return fail(MWAX_E_INVAL, "null configuration or output");
+    if (cfg->n_pols != 2) return fail(MWAX_E_INVAL, "n_pols must be 2 (got %d)", cfg->n_pols);
+    if (cfg->n_tiles < 1 || cfg->n_tiles > 1024)
+        return fail(MWAX_E_INVAL, "n_tiles must be in 1..1024 (got %d)", cfg->n_tiles);
+    if (!(cfg->coarse_bw_hz > 0) || !std::isfinite(cfg->coarse_bw_hz))
+        return fail(MWAX_E_INVAL, "coarse_bw_hz must be positive");
+    if (!(cfg->fine_chan_hz > 0) || !std::isfinite(cfg->fine_chan_hz))
+        return fail(MWAX_E_INVAL, "fine_chan_hz must be positive");
+    const double lf = cfg->coarse_bw_hz / cfg->fine_chan_hz;
+    const int64_t L = llround(lf);
+    if (L < 1 || std::fabs(lf - (double)L) > 1e-9 * lf)
+        return fail(MWAX_E_INVAL, "coarse_bw/fine_chan = %.9g is not a whole number of channels", lf);
+    if (!is_pow2(L) || L > 1024)
+        return fail(MWAX_E_UNSUPPORTED, "FFT length %lld: only powers of two 1..1024 are implemented",
+                    (long long)L);
+    if (!(cfg->int_time_s > 0) || !std::isfinite(cfg->int_time_s))
+        return fail(MWAX_E_INVAL, "int_time_s must be positive");
+    const double tf = cfg->int_time_s * cfg->coarse_bw_hz / (double)L;
+    const int64_t T = llround(tf);
+    if (T < 1 || std::fabs(tf - (double)T) > 1e-9 * std::max(1.0, tf))
+        return fail(MWAX_E_INVAL, "int_time * coarse_bw / L = %.9g must be a whole number of spectra >= 1", tf);
+    if (cfg->xprec < MWAX_X_FP32 || cfg->xprec > MWAX_X_INT8)
+        return fail(MWAX_E_INVAL, "unknown xprec %d", cfg->xprec);
+    if (cfg->reserved != 0 || cfg->flags != 0) return fail(MWAX_E_INVAL, "reserved fields and flags must be 0");
+    if (cfg->max_samples < L || cfg->max_samples % L != 0)
+        return fail(MWAX_E_INVAL, "max_samples must be a positive multiple of L = %lld", (long long)L);
+
+    std::memset(o, 0, sizeof *o);
+    const int64_t n_in = 2 * (int64_t)cfg->n_tiles;
+    o->n_inputs = (int32_t)n_in;
+    o->fft_len = (int32_t)L;
+    o->spectra_per_int = T;
+    o->n_pairs = n_in * (n_in + 1) / 2;
+    o->n_baselines = (int64_t)cfg->n_tiles * (cfg->n_tiles + 1) / 2;
+    o->max_spectra = cfg->max_samples / L;
+    const int64_t segs = (o->max_spectra + T - 1) / T + 1;     // integrations one call can touch
+    o->n_slots = (int32_t)(segs + 1);
+    o->group = group_of(cfg->xprec);
+    o->vis_per_int = L * o->n_pairs;
+    o->cal_spectra = std::min<int64_t>(T, (kCalSamples + L - 1) / L);
+    const int64_t NG = (o->max_spectra + o->group - 1) / o->group + segs;
+    const uint64_t chan_b = (uint64_t)L * NG * n_in * kRowBytes;
+    const uint64_t integ_b = (uint64_t)o->n_slots * L * o->n_pairs * 16;
+    const uint64_t small_b = (uint64_t)o->n_slots * 2 * L * 4 + 4 * L * 4 + L * 8 + (uint64_t)kStatsMaxWG * L * 8;
+    o->workspace_bytes = chan_b + integ_b + small_b;
+    o->sample_time_s = 1.0 / cfg->coarse_bw_hz;
+    o->fine_chan_hz = cfg->coarse_bw_hz / (double)L;
+    o->int_time_s = (double)T * (double)L / cfg->coarse_bw_hz;
+    return MWAX_OK;
+}
+
+void free_plan(mwax_plan p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto &e : p->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto e : p->pool) (void)hipEventDestroy(e);
+    (void)hipFree(p->chan);
+    (void)hipFree(p->integ);
+    (void)hipFree(p->scales);
+    (void)hipFree(p->fixed);
+    (void)hipFree(p->ones);
+    (void)hipFree(p->tw);
+    (void)hipFree(p->stats);
+    delete p;
+}
+
+// Split a block of M spectra at integration boundaries and check slot use.
+mwax_status plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out) {
+    out.clear();
+    int64_t g = p->g_chan, done = 0, grp = 0;
+    while (done < M) {
+        Segment s;
+        s.j = g / p->T;
+        s.local0 = g - s.j * p->T;
+        s.nframes = std::min(p->T - s.local0, M - done);
+        s.slot = (int)(s.j % p->nslots);
+        s.frame0 = done;
+        s.grp0 = grp;
+        s.ngrp = (s.nframes + p->G - 1) / p->G;
+        grp += s.ngrp;
+        g += s.nframes;
+        done += s.nframes;
+        out.push_back(s);
+    }
+    if (grp > p->NG) return fail(MWAX_E_INVAL, "block needs %lld row groups, buffer holds %lld",
+                                 (long long)grp, (long long)p->NG);
+    for (const Segment &s : out) {
+        const int64_t owner = p->slot_owner[s.slot];
+        if (s.local0 == 0) {
+            if (owner != -1)
+                return fail(MWAX_E_STATE,
+                            "integration %lld needs device slot %d, still held by integration %lld: "
+                            "call mwax_integrate first", (long long)s.j, s.slot, (long long)owner);
+        } else if (owner != s.j) {
+            return fail(MWAX_E_STATE, "integration %lld lost its slot", (long long)s.j);
+        }
+    }
+    return MWAX_OK;
+}
+
+// Set the scales of the integrations that begin in this block (INT8 plans).
+mwax_status begin_integrations(mwax_plan p, const int8_t *volts, int64_t ld, bool from_voltages) {
+    for (const Segment &s : p->segs) {
+        if (s.local0 != 0) continue;
+        p->slot_owner[s.slot] = s.j;
+        p->slot_count[s.slot] = 0;
+        if (p->xprec != MWAX_X_INT8) continue;
+        float *dst = p->scales + (size_t)s.slot * 2 * p->L;
+        hipError_t e;
+        if (p->fixed_mode || !from_voltages) {
+            e = launch_copy_scales(p->fixed_mode ? p->fixed : p->ones, dst, 2 * p->L, p->stream);
+        } else {
+            const int64_t ncal = std::min(p->d.cal_spectra, s.nframes);
+            FArgs a{};
+            a.volts = volts;
+            a.ld = ld;
+            a.frame0 = s.frame0;
+            a.nframes = ncal;
+            a.n_in = p->n_in;
+            a.R = p->R;
+            a.ngrp = (int32_t)((ncal + p->G - 1) / p->G);
+            a.stats_mode = 1;
+            a.tw = p->tw;
+            a.stats = p->stats;
+            e = timed(p, 0, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
+            if (e == hipSuccess) {
+                const int nwg = fengine_grid(p->n_in, p->R, a.ngrp, true);
+                e = timed(p, 0, [&] {
+                    return launch_calib_finish(p->stats, nwg, p->L, (double)ncal * p->n_in, dst, p->stream);
+                });
+            }
+        }
+        if (e != hipSuccess) return hip_fail(e, "scale calibration launch");
+    }
+    return MWAX_OK;
+}
+
+mwax_status check_plan(mwax_plan p) {
+    if (!p) return fail(MWAX_E_INVAL, "null plan");
+    return MWAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mwax_last_error(void) { return g_last_error.c_str(); }
+
+mwax_status mwax_plan_derive(const mwax_config *cfg, mwax_dims *out) {
+    mwax_status s = derive(cfg, out);
+    return s == MWAX_OK ? ok() : s;
+}
+
+mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out) {
+    if (!out) return fail(MWAX_E_INVAL, "null output handle");
+    *out = nullptr;
+    mwax_dims d;
+    mwax_status st = derive(cfg, &d);
+    if (st != MWAX_OK) return st;
+
+    mwax_plan p = new (std::nothrow) mwax_plan_s;
+    if (!p) return fail(MWAX_E_NOMEM, "host allocation failed");
+    p->cfg = *cfg;
+    p->d = d;
+    p->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&p->device);
+    p->L = d.fft_len;
+    p->G = d.group;
+    p->n_in = d.n_inputs;
+    p->xprec = cfg->xprec;
+    p->T = d.spectra_per_int;
+    p->P = d.n_pairs;
+    p->nslots = d.n_slots;
+    int lds_limit = 0;
+    if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
+        lds_limit <= 0)
+        lds_limit = 65536;
+    if (lds_limit > kMaxLds) lds_limit = kMaxLds;
+    p->R = fengine_pick_R(p->L, p->xprec, p->n_in, lds_limit);
+    if (fengine_lds_bytes(p->L, p->xprec, p->R, false) > lds_limit ||
+        fengine_lds_bytes(p->L, p->xprec, p->R, true) > lds_limit) {
+        mwax_status r = fail(MWAX_E_UNSUPPORTED, "F-engine for L = %d needs %d bytes of LDS, device allows %d",
+                             p->L, fengine_lds_bytes(p->L, p->xprec, p->R, false), lds_limit);
+        delete p;
+        return r;
+    }
+    const int nt = (p->n_in + xengine_tile(p->xprec) - 1) / xengine_tile(p->xprec);
+    p->ntiles = nt * (nt + 1) / 2;
+    const int64_t segs = (d.max_spectra + p->T - 1) / p->T + 1;
+    p->NG = (d.max_spectra + p->G - 1) / p->G + segs;
+    p->slot_bytes = (size_t)p->L * p->P * 16;
+    p->slot_owner.assign(p->nslots, -1);
+    p->slot_count.assign(p->nslots, 0);
+
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+    };
+    alloc((void **)&p->chan, (size_t)p->L * p->NG * p->n_in * kRowBytes);
+    alloc(&p->integ, p->slot_bytes * p->nslots);
+    alloc((void **)&p->scales, (size_t)p->nslots * 2 * p->L * sizeof(float));
+    alloc((void **)&p->fixed, (size_t)2 * p->L * sizeof(float));
+    alloc((void **)&p->ones, (size_t)2 * p->L * sizeof(float));
+    alloc((void **)&p->tw, (size_t)p->L * sizeof(float2));
+    alloc((void **)&p->stats, (size_t)kStatsMaxWG * p->L * sizeof(double));
+    if (e != hipSuccess) {
+        mwax_status r = hip_fail(e, "workspace allocation");
+        free_plan(p);
+        return r;
+    }
+    std::vector<float> ones(2 * p->L, 1.0f);
+    e = hipMemcpyAsync(p->ones, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->fixed, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = launch_twiddles(p->tw, p->L, p->stream);
+    if (e == hipSuccess) e = launch_fill_zero(p->integ, p->slot_bytes * p->nslots, p->stream);
+    if (e == hipSuccess) e = launch_copy_scales(p->ones, p->scales, 2 * p->L, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        mwax_status r = hip_fail(e, "plan initialisation");
+        free_plan(p);
+        return r;
+    }
+    *out = p;
+    return ok();
+}
+
+mwax_status mwax_plan_destroy(mwax_plan p) {
+    free_plan(p);
+    return ok();
+}
+
+mwax_status mwax_plan_get_dims(mwax_plan p, mwax_dims *out) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!out) return fail(MWAX_E_INVAL, "null output");
+    *out = p->d;
+    return ok();
+}
+
+mwax_status mwax_channelise(mwax_plan p, const int8_t *d_volts, int64_t n_samples, int64_t ld_samples) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!d_volts) return fail(MWAX_E_INVAL, "null voltage pointer");
+    if ((uintptr_t)d_volts & 15) return fail(MWAX_E_INVAL, "voltages must be 16-byte aligned");
+    if (n_samples <= 0 || n_samples % p->L != 0 || n_samples > p->cfg.max_samples)
+        return fail(MWAX_E_INVAL, "n_samples = %lld must be a positive multiple of L = %d and <= max_samples = %lld",
+                    (long long)n_samples, p->L, (long long)p->cfg.max_samples);
+    if (ld_samples < n_samples || ld_samples % 8 != 0)
+        return fail(MWAX_E_INVAL, "ld_samples = %lld must be >= n_samples and a multiple of 8", (long long)ld_samples);
+    if (p->pending) return fail(MWAX_E_STATE, "the previous channelised block has not been correlated");
+    const int64_t M = n_samples / p->L;
+    std::vector<Segment> segs;
+    mwax_status st = plan_segments(p, M, segs);
+    if (st != MWAX_OK) return st;
+    p->segs = segs;
+    st = begin_integrations(p, d_volts, ld_samples, true);
+    if (st != MWAX_OK) return st;
+    const float half_scale = std::ldexp(1.0f, -fp16_exponent(p->L));
+    for (const Segment &s : p->segs) {
+        FArgs a{};
+        a.volts = d_volts;
+        a.ld = ld_samples;
+        a.frame0 = s.frame0;
+        a.nframes = s.nframes;
+        a.chan = p->chan;
+        a.NG = p->NG;
+        a.grp0 = s.grp0;
+        a.n_in = p->n_in;
+        a.R = p->R;
+        a.ngrp = (int32_t)s.ngrp;
+        a.stats_mode = 0;
+        a.tw = p->tw;
+        a.inv_s = p->scales + (size_t)s.slot * 2 * p->L + p->L;
+        a.half_scale = half_scale;
+        hipError_t e = timed(p, 0, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
+        if (e != hipSuccess) return hip_fail(e, "F-engine launch");
+    }
+    p->pending = true;
+    p->have_block = true;
+    p->block_spectra = M;
+    p->g_chan += M;
+    return ok();
+}
+
+mwax_status mwax_load_channelised(mwax_plan p, const void *d_chan, int64_t n_spectra) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!d_chan) return fail(MWAX_E_INVAL, "null channelised pointer");
+    if (n_spectra <= 0 || n_spectra > p->d.max_spectra)
+        return fail(MWAX_E_INVAL, "n_spectra = %lld must be in 1..max_spectra = %lld", (long long)n_spectra,
+                    (long long)p->d.max_spectra);
+    const int esize = p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4);
+    if ((uintptr_t)d_chan % esize) return fail(MWAX_E_INVAL, "channelised data misaligned");
+    if (p->pending) return fail(MWAX_E_STATE, "the previous channelised block has not been correlated");
+    std::vector<Segment> segs;
+    mwax_status st = plan_segments(p, n_spectra, segs);
+    if (st != MWAX_OK) return st;
+    p->segs = segs;
+    st = begin_integrations(p, nullptr, 0, false);
+    if (st != MWAX_OK) return st;
+    for (const Segment &s : p->segs) {
+        RepackArgs a{};
+        a.canon = const_cast<void *>(d_chan);
+        a.m0 = s.frame0;
+        a.nframes = s.nframes;
+        a.chan = p->chan;
+        a.NG = p->NG;
+        a.grp0 = s.grp0;
+        a.n_in = p->n_in;
+        a.L = p->L;
+        a.G = p->G;
+        a.esize = esize;
+        a.to_internal = 1;
+        hipError_t e = launch_repack(a, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "load launch");
+    }
+    p->pending = true;
+    p->have_block = true;
+    p->block_spectra = n_spectra;
+    p->g_chan += n_spectra;
+    return ok();
+}
+
+mwax_status mwax_read_channelised(mwax_plan p, void *d_out, int64_t max_spectra, int64_t *n_spectra) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!d_out || !n_spectra) return fail(MWAX_E_INVAL, "null output");
+    if (!p->have_block) return fail(MWAX_E_STATE, "nothing has been channelised");
+    if (p->block_spectra > max_spectra)
+        return fail(MWAX_E_INVAL, "block holds %lld spectra, output room for %lld", (long long)p->block_spectra,
+                    (long long)max_spectra);
+    const int esize = p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4);
+    for (const Segment &s : p->segs) {
+        RepackArgs a{};
+        a.canon = d_out;
+        a.m0 = s.frame0;
+        a.nframes = s.nframes;
+        a.chan = p->chan;
+        a.NG = p->NG;
+        a.grp0 = s.grp0;
+        a.n_in = p->n_in;
+        a.L = p->L;
+        a.G = p->G;
+        a.esize = esize;
+        a.to_internal = 0;
+        hipError_t e = launch_repack(a, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "read launch");
+    }
+    *n_spectra = p->block_spectra;
+    return ok();
+}
+
+mwax_status mwax_correlate(mwax_plan p) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!p->pending) return fail(MWAX_E_STATE, "no fresh channelised block to correlate");
+    for (const Segment &s : p->segs) {
+        XArgs a{};
+        a.chan = p->chan;
+        a.NG = p->NG;
+        a.grp0 = s.grp0;
+        a.ngrp = (int32_t)s.ngrp;
+        a.n_in = p->n_in;
+        a.L = p->L;
+        a.ntiles = p->ntiles;
+        a.tile = xengine_tile(p->xprec);
+        a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
+        a.P = p->P;
+        hipError_t e = timed(p, 1, [&] { return launch_xengine(p->xprec, a, p->stream); });
+        if (e != hipSuccess) return hip_fail(e, "X-engine launch");
+        p->slot_count[s.slot] += s.nframes;
+    }
+    p->pending = false;
+    return ok();
+}
+
+static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_ints, int32_t *n_emitted,
+                        int32_t order) {
+    int32_t n = 0;
+    const double post = p->xprec == MWAX_X_FP16 ? std::ldexp(1.0, 2 * fp16_exponent(p->L)) : 1.0;
+    const size_t per_int = order == MWAX_ORDER_TILE_BL ? (size_t)p->d.n_baselines * p->L * 4 : (size_t)p->L * p->P;
+    const size_t esz = order == 2 ? 16 : 8;
+    while (n < max_ints) {
+        const int64_t j = p->next_emit;
+        const int slot = (int)(j % p->nslots);
+        if (p->slot_owner[slot] != j || p->slot_count[slot] < p->T) break;
+        PackArgs a{};
+        a.integ = (uint8_t *)p->integ + (size_t)slot * p->slot_bytes;
+        a.is_int = p->xprec == MWAX_X_INT8;
+        a.scales = p->scales + (size_t)slot * 2 * p->L;
+        a.post = post;
+        a.out = (uint8_t *)d_vis + (size_t)n * per_int * esz;
+        a.scales_out = d_scales ? d_scales + (size_t)n * p->L : nullptr;
+        a.order = order;
+        a.L = p->L;
+        a.n_in = p->n_in;
+        a.P = p->P;
+        hipError_t e = timed(p, 2, [&] { return launch_pack(a, p->stream); });
+        if (e != hipSuccess) return hip_fail(e, "pack launch");
+        p->slot_owner[slot] = -1;
+        p->slot_count[slot] = 0;
+        ++p->next_emit;
+        ++n;
+    }
+    *n_emitted = n;
+    return ok();
+}
+
+mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *n_emitted, int32_t order) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!n_emitted) return fail(MWAX_E_INVAL, "null n_emitted");
+    *n_emitted = 0;
+    if (max_ints < 0 || (max_ints > 0 && !d_vis)) return fail(MWAX_E_INVAL, "bad output buffer");
+    if (order != MWAX_ORDER_CHAN_TRI && order != MWAX_ORDER_TILE_BL) return fail(MWAX_E_INVAL, "unknown order %d", order);
+    if (((uintptr_t)d_vis & 7) != 0) return fail(MWAX_E_INVAL, "output must be 8-byte aligned");
+    return emit(p, d_vis, nullptr, max_ints, n_emitted, order);
+}
+
+mwax_status mwax_integrate_raw_i64(mwax_plan p, int64_t *d_vis, float *d_scales, int32_t max_ints,
+                                   int32_t *n_emitted) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!n_emitted) return fail(MWAX_E_INVAL, "null n_emitted");
+    *n_emitted = 0;
+    if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "raw int64 output exists for INT8 plans only");
+    if (max_ints < 0 || (max_ints > 0 && !d_vis)) return fail(MWAX_E_INVAL, "bad output buffer");
+    if (((uintptr_t)d_vis & 15) != 0) return fail(MWAX_E_INVAL, "output must be 16-byte aligned");
+    return emit(p, d_vis, d_scales, max_ints, n_emitted, 2);
+}
+
+static bool integration_in_progress(mwax_plan p) {
+    if (p->pending) return true;
+    for (int s = 0; s < p->nslots; ++s)
+        if (p->slot_owner[s] != -1 && p->slot_count[s] < p->T) return true;
+    return false;
+}
+
+mwax_status mwax_set_scales(mwax_plan p, const float *h_scales) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "scales exist for INT8 plans only");
+    if (!h_scales) return fail(MWAX_E_INVAL, "null scales");
+    if (integration_in_progress(p)) return fail(MWAX_E_STATE, "an integration is in progress");
+    std::vector<float> v(2 * p->L);
+    for (int c = 0; c < p->L; ++c) {
+        const float s = h_scales[c];
+        if (!(s > 0.0f) || !std::isfinite(s)) return fail(MWAX_E_INVAL, "scale %d must be finite and > 0", c);
+        v[c] = s;
+        v[p->L + c] = 1.0f / s;
+    }
+    hipError_t e = hipMemcpyAsync(p->fixed, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "scale upload");
+    p->fixed_mode = true;
+    return ok();
+}
+
+mwax_status mwax_auto_scales(mwax_plan p) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "scales exist for INT8 plans only");
+    if (integration_in_progress(p)) return fail(MWAX_E_STATE, "an integration is in progress");
+    p->fixed_mode = false;
+    return ok();
+}
+
+mwax_status mwax_reset(mwax_plan p) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    hipError_t e = launch_fill_zero(p->integ, p->slot_bytes * p->nslots, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "reset");
+    std::fill(p->slot_owner.begin(), p->slot_owner.end(), -1);
+    std::fill(p->slot_count.begin(), p->slot_count.end(), 0);
+    p->g_chan = 0;
+    p->next_emit = 0;
+    p->pending = false;
+    p->have_block = false;
+    p->segs.clear();
+    return ok();
+}
+
+mwax_status mwax_sync(mwax_plan p) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronisation");
+    return ok();
+}
+
+mwax_status mwax_set_timing(mwax_plan p, int32_t enable) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    p->timing = enable != 0;
+    return ok();
+}
+
+mwax_status mwax_kernel_time(mwax_plan p, int32_t family, double *total_ms, int64_t *launches) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (family < 0 || family > 2 || !total_ms || !launches) return fail(MWAX_E_INVAL, "bad arguments");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronisation");
+    for (auto &ev : p->events) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+            p->t_ms[ev.fam] += ms;
+            p->t_n[ev.fam] += 1;
+        }
+        p->pool.push_back(ev.a);
+        p->pool.push_back(ev.b);
+    }
+    p->events.clear();
+    *total_ms = p->t_ms[family];
+    *launches = p->t_n[family];
+    p->t_ms[family] = 0.0;
+    p->t_n[family] = 0;
+    return ok();
+}
+
+}  // extern "C"

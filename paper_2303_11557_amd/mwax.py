@@ -1,0 +1,254 @@
+"""ctypes binding of libmwax (C ABI in include/mwax.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of ``libmwax.so``; PyTorch provides device memory and the stream.  There is no
+CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmwax.so")
+
+MWAX_OK, MWAX_E_INVAL, MWAX_E_NOMEM, MWAX_E_DEVICE, MWAX_E_STATE, MWAX_E_UNSUPPORTED = range(6)
+X_FP32, X_FP16, X_INT8 = 0, 1, 2
+ORDER_CHAN_TRI, ORDER_TILE_BL = 0, 1
+FAMILY_F, FAMILY_X, FAMILY_PACK = 0, 1, 2
+F_S = 1.28e6
+
+_PREC = {"fp32": X_FP32, "fp16": X_FP16, "int8": X_INT8}
+_ORDER = {"tri": ORDER_CHAN_TRI, "tile_bl": ORDER_TILE_BL}
+
+EXPORTS = (
+    "mwax_plan_derive", "mwax_plan_create", "mwax_plan_destroy", "mwax_plan_get_dims",
+    "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
+    "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales",
+    "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
+)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_tiles", ctypes.c_int32), ("n_pols", ctypes.c_int32),
+        ("coarse_bw_hz", ctypes.c_double), ("fine_chan_hz", ctypes.c_double),
+        ("int_time_s", ctypes.c_double), ("xprec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("max_samples", ctypes.c_int64), ("flags", ctypes.c_uint64),
+    ]
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [
+        ("n_inputs", ctypes.c_int32), ("fft_len", ctypes.c_int32),
+        ("spectra_per_int", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+        ("n_baselines", ctypes.c_int64), ("max_spectra", ctypes.c_int64),
+        ("n_slots", ctypes.c_int32), ("group", ctypes.c_int32),
+        ("vis_per_int", ctypes.c_int64), ("cal_spectra", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_uint64), ("sample_time_s", ctypes.c_double),
+        ("fine_chan_hz", ctypes.c_double), ("int_time_s", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MwaxError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"mwax error {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libmwax.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmwax is not built ({LIB_PATH} missing): run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        P = ctypes.POINTER
+        sig = {
+            "mwax_plan_derive": [P(Config), P(Dims)],
+            "mwax_plan_create": [P(Config), vp, P(vp)],
+            "mwax_plan_destroy": [vp],
+            "mwax_plan_get_dims": [vp, P(Dims)],
+            "mwax_channelise": [vp, vp, i64, i64],
+            "mwax_load_channelised": [vp, vp, i64],
+            "mwax_read_channelised": [vp, vp, i64, P(i64)],
+            "mwax_correlate": [vp],
+            "mwax_integrate": [vp, vp, i32, P(i32), i32],
+            "mwax_integrate_raw_i64": [vp, vp, vp, i32, P(i32)],
+            "mwax_set_scales": [vp, P(ctypes.c_float)],
+            "mwax_auto_scales": [vp],
+            "mwax_reset": [vp],
+            "mwax_sync": [vp],
+            "mwax_set_timing": [vp, i32],
+            "mwax_kernel_time": [vp, i32, P(ctypes.c_double), P(i64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.mwax_last_error.argtypes = []
+        L.mwax_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != MWAX_OK:
+        raise MwaxError(status, lib().mwax_last_error().decode())
+
+
+def make_config(n_tiles, L=None, fine_chan_hz=None, T=None, int_time_s=None, xprec="fp32",
+                max_samples=None, coarse_bw_hz=F_S) -> Config:
+    if fine_chan_hz is None:
+        fine_chan_hz = coarse_bw_hz / L
+    if L is None:
+        L = int(round(coarse_bw_hz / fine_chan_hz))
+    if int_time_s is None:
+        int_time_s = T * L / coarse_bw_hz
+    if max_samples is None:
+        max_samples = int(round(int_time_s * coarse_bw_hz))
+    prec = _PREC[xprec] if isinstance(xprec, str) else int(xprec)
+    return Config(int(n_tiles), 2, float(coarse_bw_hz), float(fine_chan_hz), float(int_time_s),
+                  prec, 0, int(max_samples), 0)
+
+
+def derive(cfg: Config) -> Dims:
+    d = Dims()
+    _check(lib().mwax_plan_derive(ctypes.byref(cfg), ctypes.byref(d)))
+    return d
+
+
+class Plan:
+    """One correlator plan on the current device and torch's current stream."""
+
+    def __init__(self, cfg: Config, stream=None):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().mwax_plan_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.byref(h)))
+        self.h = h
+        d = Dims()
+        _check(lib().mwax_plan_get_dims(self.h, ctypes.byref(d)))
+        self.dims = d
+        self.L = d.fft_len
+        self.n_in = d.n_inputs
+        self.P = d.n_pairs
+        self.T = d.spectra_per_int
+        self.xprec = cfg.xprec
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().mwax_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- hot path -------------------------------------------------------------
+    def channelise(self, volts, n_samples=None):
+        """volts: int8 cuda tensor [n_inputs][>= n_samples][2], rows may be strided."""
+        t = self.torch
+        assert volts.dtype == t.int8 and volts.is_cuda and volts.dim() == 3
+        assert volts.shape[0] == self.n_in and volts.shape[2] == 2
+        assert volts.stride(2) == 1 and volts.stride(1) == 2
+        n = volts.shape[1] if n_samples is None else int(n_samples)
+        ld = volts.stride(0) // 2
+        _check(lib().mwax_channelise(self.h, ctypes.c_void_p(volts.data_ptr()), n, ld))
+
+    def load_channelised(self, chan):
+        """chan: [n_spectra][L][n_inputs][2] of int8 / int16 (binary16 bits) / float32."""
+        assert chan.is_cuda and chan.is_contiguous() and chan.dim() == 4
+        assert chan.shape[1] == self.L and chan.shape[2] == self.n_in and chan.shape[3] == 2
+        _check(lib().mwax_load_channelised(self.h, ctypes.c_void_p(chan.data_ptr()), chan.shape[0]))
+
+    def element_dtype(self):
+        t = self.torch
+        return {X_INT8: t.int8, X_FP16: t.float16, X_FP32: t.float32}[self.xprec]
+
+    def read_channelised(self):
+        t = self.torch
+        out = t.empty((self.dims.max_spectra, self.L, self.n_in, 2), dtype=self.element_dtype(),
+                      device="cuda")
+        n = ctypes.c_int64()
+        _check(lib().mwax_read_channelised(self.h, ctypes.c_void_p(out.data_ptr()),
+                                           self.dims.max_spectra, ctypes.byref(n)))
+        return out[: n.value]
+
+    def correlate(self):
+        _check(lib().mwax_correlate(self.h))
+
+    def integrate(self, max_ints=1, order="tri", out=None):
+        """Emit up to max_ints completed integrations -> complex64 tensor [n][...]."""
+        t = self.torch
+        o = _ORDER[order] if isinstance(order, str) else int(order)
+        if out is None:
+            if o == ORDER_CHAN_TRI:
+                shape = (max_ints, self.L, self.P)
+            else:
+                shape = (max_ints, self.dims.n_baselines, self.L, 4)
+            out = t.empty(shape, dtype=t.complex64, device="cuda")
+        n = ctypes.c_int32()
+        _check(lib().mwax_integrate(self.h, ctypes.c_void_p(out.data_ptr()), max_ints,
+                                    ctypes.byref(n), o))
+        return out[: n.value]
+
+    def integrate_raw(self, max_ints=1):
+        """INT8 plans: exact int64 sums [n][L][P][2] and the scales s_c [n][L]."""
+        t = self.torch
+        out = t.empty((max_ints, self.L, self.P, 2), dtype=t.int64, device="cuda")
+        sc = t.empty((max_ints, self.L), dtype=t.float32, device="cuda")
+        n = ctypes.c_int32()
+        _check(lib().mwax_integrate_raw_i64(self.h, ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(sc.data_ptr()), max_ints,
+                                            ctypes.byref(n)))
+        return out[: n.value], sc[: n.value]
+
+    def set_scales(self, scales):
+        import numpy as np
+        a = np.ascontiguousarray(scales, dtype=np.float32)
+        assert a.shape == (self.L,)
+        _check(lib().mwax_set_scales(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def auto_scales(self):
+        _check(lib().mwax_auto_scales(self.h))
+
+    def reset(self):
+        _check(lib().mwax_reset(self.h))
+
+    def sync(self):
+        _check(lib().mwax_sync(self.h))
+
+    def set_timing(self, on=True):
+        _check(lib().mwax_set_timing(self.h, int(bool(on))))
+
+    def kernel_time(self, family):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().mwax_kernel_time(self.h, family, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def pair_index(n1, n2):
+    return n1 * (n1 + 1) // 2 + n2
