@@ -14,6 +14,8 @@
 // exchange of the L1 x L2 block through LDS, pass 2 in registers.  The
 // quantised outputs are written to an LDS image of the workgroup's output rows,
 // which is then stored with coalesced 16-byte writes.
+#include <algorithm>
+
 #include "mwax_internal.h"
 
 namespace mwax {
@@ -49,19 +51,20 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// b * W_N^e with W_N^e read from the W_L table at index e * TS (TS = L / N).
-// e = 0 and e = N/4 are exact (1 and -i).
-template <int N, int TS>
-__device__ __forceinline__ float2 tw_mul(float2 b, int e, const float2 *__restrict__ tw) {
+// b * W_N^e with w[j] = W_N^j held in registers; e = 0 and e = N/4 are exact
+// (1 and -i) and need no multiply.
+template <int N>
+__device__ __forceinline__ float2 tw_mul(float2 b, int e, const float2 *w) {
     if (e == 0) return b;
     if (4 * e == N) return make_float2(b.y, -b.x);
-    const float2 w = tw[e * TS];
-    return make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+    const float2 t = w[e];
+    return make_float2(b.x * t.x - b.y * t.y, b.x * t.y + b.y * t.x);
 }
 
-// In-register radix-2 decimation-in-time DFT of N points, natural order in and out.
-template <int N, int TS>
-__device__ __forceinline__ void dft_regs(float2 *v, const float2 *__restrict__ tw) {
+// In-register radix-2 decimation-in-time DFT of N points, natural order in and
+// out; w[j] = W_N^j for j < N/2.
+template <int N>
+__device__ __forceinline__ void dft_regs(float2 *v, const float2 *w) {
     if constexpr (N > 1) {
         float2 t[N];
 #pragma unroll
@@ -73,7 +76,7 @@ __device__ __forceinline__ void dft_regs(float2 *v, const float2 *__restrict__ t
             for (int base = 0; base < N; base += 2 * h) {
 #pragma unroll
                 for (int j = 0; j < h; ++j) {
-                    const float2 b = tw_mul<N, TS>(t[base + j + h], j * (N / (2 * h)), tw);
+                    const float2 b = tw_mul<N>(t[base + j + h], j * (N / (2 * h)), w);
                     const float2 a = t[base + j];
                     t[base + j] = make_float2(a.x + b.x, a.y + b.y);
                     t[base + j + h] = make_float2(a.x - b.x, a.y - b.y);
@@ -105,74 +108,99 @@ __device__ __forceinline__ int chan_of(int r, int i) {
     return (k + L / 2) & (L - 1);
 }
 
-// Requantisation rule of the INT8 X-engine: q = clamp(rne(x), -127, 127).
-__device__ __forceinline__ int8_t quant8(float x) {
-    return (int8_t)(int)fminf(fmaxf(rintf(x), -127.0f), 127.0f);
-}
-
-template <int XP>
-__device__ __forceinline__ void put_out(uint8_t *row, int f, float2 X, float sc) {
-    if constexpr (XP == MWAX_X_INT8) {
-        row[f] = (uint8_t)quant8(X.x * sc);
-        row[16 + f] = (uint8_t)quant8(X.y * sc);
-    } else if constexpr (XP == MWAX_X_FP16) {
-        *reinterpret_cast<_Float16 *>(row + 2 * f) = (_Float16)(X.x * sc);
-        *reinterpret_cast<_Float16 *>(row + 16 + 2 * f) = (_Float16)(X.y * sc);
-    } else {
-        *reinterpret_cast<float *>(row + 4 * f) = X.x;
-        *reinterpret_cast<float *>(row + 16 + 4 * f) = X.y;
-    }
-}
-
 constexpr int kThreads = 256;
 
+// Output-image padding per channel (bytes beyond R * 32), chosen so the packed
+// output writes of a wave fall in distinct LDS banks.
+constexpr int cp_pad(int L, int XP) {
+    return L <= 16 ? 4 : (L == 32 ? (XP == MWAX_X_INT8 ? 8 : 4)
+                       : (L == 64 ? (XP == MWAX_X_INT8 ? 8 : 16)
+                       : (L <= 256 ? (XP == MWAX_X_INT8 ? 4 : 8) : 4)));
+}
+
+// Work decomposition of one workgroup (4 waves, 256 threads) for length L and
+// output precision XP.  An FFT group is L2 lanes; a wave holds GPW groups.
+// Each group transforms FPG consecutive frames of one input, so that the
+// results of FPG frames leave in one packed LDS write; the workgroup covers
+// R inputs x G frames (one 32-byte row group per channel and input).
+template <int L, int XP>
+struct FCfg {
+    using SH = FftShape<L>;
+    static constexpr int L1 = SH::L1, L2 = SH::L2, U = SH::U;
+    static constexpr int G = PrecTraits<XP>::G, ES = PrecTraits<XP>::ES;
+    static constexpr int FPG = XP == MWAX_X_INT8 ? 2 : (XP == MWAX_X_FP16 && L <= 256 ? 2 : 1);
+    static constexpr int GPW = 64 / L2;
+    static constexpr int NGWG = 4 * GPW;          // FFT groups per workgroup
+    static constexpr int PACKS = G / FPG;         // frame packs per input
+    static constexpr int R = NGWG / PACKS;        // inputs per workgroup item
+    static constexpr int CP = R * kRowBytes + cp_pad(L, XP);
+    static constexpr int SP = 2 * L + 16;         // staged frame pitch (bytes)
+    static constexpr int EXG = L + 8;             // exchange pitch per group (float2)
+    static constexpr int OUT_BYTES = L * CP;
+    static constexpr int STAGE_BYTES = L2 > 1 ? R * G * SP : 0;
+    static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * 8 : 0;
+    static constexpr int RED_BYTES = kThreads * L1 * 4;
+    static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
+};
+
+// Magic-number rounding: fma(x, s, 1.5 * 2^23) rounds the exact product x * s to
+// the nearest integer, ties to even, and keeps it in the low mantissa bits;
+// clamping to 1.5 * 2^23 +- 127 then leaves the two's-complement int8 code in
+// the low byte.  This is the requantisation rule q = clamp(rne(x s), -127, 127)
+// evaluated on the FP32 spectrum x and FP32 scale s.
+constexpr float kMagic = 12582912.0f;
+__device__ __forceinline__ uint32_t quant8_bits(float x, float s) {
+    const float r = fmaf(x, s, kMagic);
+    return __float_as_uint(fminf(fmaxf(r, kMagic - 127.0f), kMagic + 127.0f));
+}
+
 template <int L>
-__host__ __device__ constexpr int ex_group_pitch() {  // float2 units per FFT group
-    return FftShape<L>::L1 * (FftShape<L>::L2 + 1) + 8;
+__device__ __forceinline__ float2 load_pair_biased(const uint8_t *p) {
+    // one complex int8 sample as (re + 128, im + 128): exact, unsigned conversion
+    const uint32_t w = (uint32_t)(*reinterpret_cast<const uint16_t *>(p)) ^ 0x8080u;
+    return make_float2((float)(w & 0xffu), (float)((w >> 8) & 0xffu));
 }
 
 template <int L, int XP, bool STATS>
 __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
-    using SH = FftShape<L>;
-    constexpr int L1 = SH::L1, L2 = SH::L2, U = SH::U;
-    constexpr int G = PrecTraits<XP>::G;
-    constexpr int GPW = 64 / L2;            // FFTs per wave per iteration
-    constexpr int FPI = 4 * GPW;            // FFTs per workgroup per iteration
-    constexpr int EXK = L2 + 1;             // exchange: float2 pitch of a k1 row
-    constexpr int EXG = ex_group_pitch<L>();
-    constexpr int SP = 2 * L + 16;          // staged frame pitch (bytes)
+    using C = FCfg<L, XP>;
+    constexpr int L1 = C::L1, L2 = C::L2, U = C::U, G = C::G, ES = C::ES, FPG = C::FPG;
+    constexpr int GPW = C::GPW, PACKS = C::PACKS, R = C::R, CP = C::CP, SP = C::SP, EXG = C::EXG;
     extern __shared__ __align__(16) uint8_t smem[];
-
-    const int R = a.R;
-    const int CP = R * kRowBytes + 16;      // output image: bytes per channel
     uint8_t *outbuf = smem;
-    uint8_t *stage = smem + (STATS ? 0 : L * CP);
-    float2 *ex = reinterpret_cast<float2 *>(stage + (L2 > 1 ? R * G * SP : 0));
+    uint8_t *stage = smem + (STATS ? 0 : C::OUT_BYTES);
+    float2 *ex = reinterpret_cast<float2 *>(stage + C::STAGE_BYTES);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = lane / L2, r = lane % L2;
+    const int gg = wave * GPW + gi;            // FFT group within the workgroup
+    const int nl = gg / PACKS;                 // its input within the item
+    const int pk = gg - nl * PACKS;            // its frame pack: frames pk*FPG + t
     const int nblk = (a.n_in + R - 1) / R;
     const int items = a.ngrp * nblk;
-    const int nfft = R * G;
 
     // Per-lane constants.  Output slot i of a lane (i = u * L2 + k2 for the
     // two-pass split) holds FFT bin k = (r U + u) + L1 k2, channel (k + L/2) mod L.
-    constexpr bool kTwReg = L1 <= 16;       // keep the inter-pass twiddles in registers
-    constexpr bool kScReg = L1 <= 16;       // keep the INT8 scales in registers
-    float2 twr[kTwReg ? L1 : 1];
-    float sc[kScReg ? L1 : 1];
+    constexpr bool kTwReg = L1 <= 16;
+    float2 w1[L1 / 2 > 0 ? L1 / 2 : 1], w2[L2 / 2 > 0 ? L2 / 2 : 1];
 #pragma unroll
-    for (int i = 0; i < L1; ++i) {
-        if constexpr (L2 > 1 && kTwReg) twr[i] = a.tw[(r * i) % L];
-        if constexpr (kScReg) {
-            if constexpr (XP == MWAX_X_INT8 && !STATS) sc[i] = a.inv_s[chan_of<L>(r, i)];
-            else if constexpr (XP == MWAX_X_FP16) sc[i] = a.half_scale;
-            else sc[i] = 1.0f;
-        }
+    for (int j = 0; j < L1 / 2; ++j) w1[j] = a.tw[j * (L / L1)];       // W_L1^j
+#pragma unroll
+    for (int j = 0; j < L2 / 2; ++j) w2[j] = a.tw[j * (L / L2)];       // W_L2^j
+    float2 twr[kTwReg && L2 > 1 ? L1 : 1];
+    if constexpr (kTwReg && L2 > 1) {
+#pragma unroll
+        for (int i = 0; i < L1; ++i) twr[i] = a.tw[(r * i) % L];        // W_L^(r k1)
+    }
+    float sc[XP == MWAX_X_INT8 && kTwReg && !STATS ? L1 : 1];
+    if constexpr (XP == MWAX_X_INT8 && kTwReg && !STATS) {
+#pragma unroll
+        for (int i = 0; i < L1; ++i) sc[i] = a.inv_s[chan_of<L>(r, i)];
     }
     float acc[STATS ? L1 : 1];
 #pragma unroll
     for (int i = 0; i < (STATS ? L1 : 1); ++i) acc[i] = 0.0f;
+    const float bias = 128.0f * (float)L;      // DC offset of the biased input
 
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int gsel = item / nblk;
@@ -185,75 +213,99 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
         __syncthreads();  // LDS of the previous item fully consumed
         if constexpr (L2 > 1) {
             constexpr int UPF = 2 * L / 16;
-            const int units = R * G * UPF;
-            for (int u = tid; u < units; u += kThreads) {
-                const int nl = u / (G * UPF);
-                const int rem = u - nl * G * UPF;
+            for (int u = tid; u < R * G * UPF; u += kThreads) {
+                const int sl = u / (G * UPF);
+                const int rem = u - sl * G * UPF;
                 const int f = rem / UPF, o = rem - f * UPF;
-                uint4 val = make_uint4(0, 0, 0, 0);
-                if (nl < nrows && f < fvalid)
+                uint4 val = make_uint4(0u, 0u, 0u, 0u);   // frames past the end are zero
+                if (sl < nrows && f < fvalid)
                     val = *reinterpret_cast<const uint4 *>(
-                        a.volts + ((int64_t)(n0 + nl) * a.ld + (src_frame + f) * L) * 2 + o * 16);
-                *reinterpret_cast<uint4 *>(stage + (nl * G + f) * SP + o * 16) = val;
+                        a.volts + ((int64_t)(n0 + sl) * a.ld + (src_frame + f) * L) * 2 + o * 16);
+                *reinterpret_cast<uint4 *>(stage + (sl * G + f) * SP + o * 16) = val;
             }
             __syncthreads();
         }
 
-        for (int it = 0; it < nfft; it += FPI) {
-            const int fi = it + wave * GPW + gi;
-            const bool live = fi < nfft;
-            const int x = live ? fi / R : 0;
-            const int nl = live ? fi - x * R : 0;
-            const int f = (x & 3) * (G / 4) + (x >> 2);   // frames 4 apart share an instruction
-            uint8_t *orow = outbuf + nl * kRowBytes;
-
-            // consume output slot i (bin of this lane) with value X
-            auto emit = [&](int i, float2 X) {
-                if (!live) return;
-                if constexpr (STATS) {
-                    acc[i] += X.x * X.x + X.y * X.y;
-                } else {
-                    const int c = chan_of<L>(r, i);
-                    float s;
-                    if constexpr (kScReg) s = sc[i];
-                    else if constexpr (XP == MWAX_X_INT8) s = a.inv_s[c];
-                    else if constexpr (XP == MWAX_X_FP16) s = a.half_scale;
-                    else s = 1.0f;
-                    put_out<XP>(orow + c * CP, f, X, s);
-                }
-            };
-
+        uint32_t q0[XP != MWAX_X_FP32 && FPG == 2 && !STATS ? 2 * L1 : 1];   // first frame of the pack
+        for (int t = 0; t < FPG; ++t) {
+            const int f = pk * FPG + t;
             float2 v[L1];
             if constexpr (L2 == 1) {
-                // whole frame per lane, straight from global memory
-                if (live && nl < nrows && f < fvalid) {
-                    const int8_t *src = a.volts + ((int64_t)(n0 + nl) * a.ld + (src_frame + f) * L) * 2;
+                if (nl < nrows && f < fvalid) {
+                    const uint8_t *src = reinterpret_cast<const uint8_t *>(a.volts) +
+                                         ((int64_t)(n0 + nl) * a.ld + (src_frame + f) * L) * 2;
                     if constexpr (L == 1) {
-                        const char2 s2 = *reinterpret_cast<const char2 *>(src);
-                        v[0] = make_float2((float)s2.x, (float)s2.y);
+                        v[0] = load_pair_biased<L>(src);
                     } else {
 #pragma unroll
                         for (int q = 0; q < L / 2; ++q) {
-                            const char4 s4 = *reinterpret_cast<const char4 *>(src + 4 * q);
-                            v[2 * q] = make_float2((float)s4.x, (float)s4.y);
-                            v[2 * q + 1] = make_float2((float)s4.z, (float)s4.w);
+                            const uint32_t wv = *reinterpret_cast<const uint32_t *>(src + 4 * q) ^ 0x80808080u;
+                            v[2 * q] = make_float2((float)(wv & 0xffu), (float)((wv >> 8) & 0xffu));
+                            v[2 * q + 1] = make_float2((float)((wv >> 16) & 0xffu), (float)(wv >> 24));
                         }
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < L; ++q) v[q] = make_float2(0.0f, 0.0f);
+                    for (int q = 0; q < L; ++q) v[q] = make_float2(128.0f, 128.0f);
                 }
-                dft_regs<L1, 1>(v, a.tw);
-#pragma unroll
-                for (int k = 0; k < L1; ++k) emit(k, v[k]);
             } else {
                 const uint8_t *fr = stage + (nl * G + f) * SP;
 #pragma unroll
-                for (int n1 = 0; n1 < L1; ++n1) {
-                    const char2 s2 = *reinterpret_cast<const char2 *>(fr + 2 * (r + L2 * n1));
-                    v[n1] = make_float2((float)s2.x, (float)s2.y);
+                for (int n1 = 0; n1 < L1; ++n1) v[n1] = load_pair_biased<L>(fr + 2 * (r + L2 * n1));
+            }
+            dft_regs<L1>(v, w1);
+
+            // consume output slot i (FFT bin of this lane) with value X
+            auto emit = [&](int i, float2 X) {
+                if (i == 0 && r == 0) {            // bin 0 carries the input bias
+                    X.x -= bias;
+                    X.y -= bias;
                 }
-                dft_regs<L1, L / L1>(v, a.tw);
+                if constexpr (STATS) {
+                    acc[i] += X.x * X.x + X.y * X.y;
+                } else {
+                    const int c = chan_of<L>(r, i);
+                    uint8_t *row = outbuf + c * CP + nl * kRowBytes + pk * FPG * ES;
+                    if constexpr (XP == MWAX_X_INT8) {
+                        float s;
+                        if constexpr (kTwReg) s = sc[i];
+                        else s = a.inv_s[c];
+                        const uint32_t br = quant8_bits(X.x, s), bi = quant8_bits(X.y, s);
+                        if (t == 0) {
+                            q0[2 * i] = br;
+                            q0[2 * i + 1] = bi;
+                        } else {
+                            // low bytes of the two frames' codes -> one 16-bit write per half
+                            *reinterpret_cast<uint16_t *>(row) = (uint16_t)__builtin_amdgcn_perm(br, q0[2 * i], 0x0c0c0400u);
+                            *reinterpret_cast<uint16_t *>(row + 16) = (uint16_t)__builtin_amdgcn_perm(bi, q0[2 * i + 1], 0x0c0c0400u);
+                        }
+                    } else if constexpr (XP == MWAX_X_FP16) {
+                        const _Float16 hr = (_Float16)(X.x * a.half_scale), hi = (_Float16)(X.y * a.half_scale);
+                        const uint32_t br = (uint32_t)__builtin_bit_cast(uint16_t, hr);
+                        const uint32_t bi = (uint32_t)__builtin_bit_cast(uint16_t, hi);
+                        if constexpr (FPG == 2) {
+                            if (t == 0) {
+                                q0[2 * i] = br;
+                                q0[2 * i + 1] = bi;
+                            } else {
+                                *reinterpret_cast<uint32_t *>(row) = q0[2 * i] | (br << 16);
+                                *reinterpret_cast<uint32_t *>(row + 16) = q0[2 * i + 1] | (bi << 16);
+                            }
+                        } else {
+                            *reinterpret_cast<uint16_t *>(row + 2 * t) = (uint16_t)br;
+                            *reinterpret_cast<uint16_t *>(row + 16 + 2 * t) = (uint16_t)bi;
+                        }
+                    } else {
+                        *reinterpret_cast<float *>(row) = X.x;
+                        *reinterpret_cast<float *>(row + 16) = X.y;
+                    }
+                }
+            };
+
+            if constexpr (L2 == 1) {
+#pragma unroll
+                for (int k = 0; k < L1; ++k) emit(k, v[k]);
+            } else {
 #pragma unroll
                 for (int k1 = 0; k1 < L1; ++k1) {
                     float2 w;
@@ -261,16 +313,19 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
                     else w = a.tw[(r * k1) % L];
                     v[k1] = make_float2(v[k1].x * w.x - v[k1].y * w.y, v[k1].x * w.y + v[k1].y * w.x);
                 }
-                float2 *eg = ex + (wave * GPW + gi) * EXG;
+                // exchange through LDS; column swizzle r ^ (k1 / U) keeps both the
+                // writes (fixed k1) and the reads (fixed r2) free of bank conflicts
+                float2 *eg = ex + gg * EXG;
 #pragma unroll
-                for (int k1 = 0; k1 < L1; ++k1) eg[k1 * EXK + r] = v[k1];
+                for (int k1 = 0; k1 < L1; ++k1) eg[k1 * L2 + (r ^ (k1 / U))] = v[k1];
                 wave_sync();
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
+                    const int k1 = r * U + u;
                     float2 w[L2];
 #pragma unroll
-                    for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[(r * U + u) * EXK + r2];
-                    dft_regs<L2, L / L2>(w, a.tw);
+                    for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[k1 * L2 + (r2 ^ r)];
+                    dft_regs<L2>(w, w2);
 #pragma unroll
                     for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2]);
                 }
@@ -285,9 +340,10 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
             for (int u = tid; u < units; u += kThreads) {
                 const int c = u / (nrows * 2);
                 const int rem = u - c * nrows * 2;
-                const int nl = rem >> 1, h = rem & 1;
-                const uint4 val = *reinterpret_cast<const uint4 *>(outbuf + c * CP + nl * kRowBytes + h * 16);
-                uint8_t *dst = a.chan + ((((int64_t)c * a.NG + a.grp0 + gsel) * a.n_in) + n0 + nl) * kRowBytes + h * 16;
+                const int sl = rem >> 1, h = rem & 1;
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(outbuf + c * CP + sl * kRowBytes + h * 16);
+                const uint4 val = make_uint4(src[0], src[1], src[2], src[3]);
+                uint8_t *dst = a.chan + ((((int64_t)c * a.NG + a.grp0 + gsel) * a.n_in) + n0 + sl) * kRowBytes + h * 16;
                 *reinterpret_cast<uint4 *>(dst) = val;
             }
         }
@@ -298,23 +354,24 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
         // hold the same channel set; sum them in a fixed order.
         __syncthreads();
         float *red = reinterpret_cast<float *>(smem);   // [kThreads / L2 slots][L2][L1]
-        const int slot = wave * GPW + gi;
 #pragma unroll
-        for (int i = 0; i < L1; ++i) red[(slot * L2 + r) * L1 + i] = acc[i];
+        for (int i = 0; i < L1; ++i) red[(gg * L2 + r) * L1 + i] = acc[i];
         __syncthreads();
         constexpr int NSLOT = kThreads / L2;
         for (int t = tid; t < L; t += kThreads) {
             const int rr = t / L1, i = t - rr * L1;
-            double s = 0.0;
-            for (int sl = 0; sl < NSLOT; ++sl) s += (double)red[(sl * L2 + rr) * L1 + i];
-            a.stats[(int64_t)blockIdx.x * L + chan_of<L>(rr, i)] = s;
+            double sum = 0.0;
+            for (int sl = 0; sl < NSLOT; ++sl) sum += (double)red[(sl * L2 + rr) * L1 + i];
+            a.stats[(int64_t)blockIdx.x * L + chan_of<L>(rr, i)] = sum;
         }
     }
 }
 
 template <int L, int XP>
 hipError_t launch_L(const FArgs &a, hipStream_t s) {
+    using C = FCfg<L, XP>;
     const bool stats = a.stats_mode != 0;
+    if (a.R != C::R) return hipErrorInvalidValue;
     const int lds = fengine_lds_bytes(L, XP, a.R, stats);
     const int grid = fengine_grid(a.n_in, a.R, a.ngrp, stats);
     if (grid < 1) return hipSuccess;
@@ -372,12 +429,21 @@ __global__ void twiddle_kernel(float2 *tw, int L) {
     tw[k] = make_float2((float)cs, (float)sn);
 }
 
+// One workgroup per channel: threads sum strided partial rows, then a fixed-order
+// tree in LDS, so the result does not depend on scheduling.
 __global__ void calib_finish_kernel(const double *stats, int nwg, int L, double count, float *scales) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= L) return;
+    __shared__ double part[256];
+    const int c = blockIdx.x;
     double t = 0.0;
-    for (int w = 0; w < nwg; ++w) t += stats[(int64_t)w * L + c];
-    const double var = t / (2.0 * count);
+    for (int w = threadIdx.x; w < nwg; w += 256) t += stats[(int64_t)w * L + c];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double var = part[0] / (2.0 * count);
     float s = 1.0f, inv = 1.0f;
     if (var > 0.0) {
         const double sd = sqrt(var);
@@ -430,18 +496,30 @@ __global__ void repack_kernel(RepackArgs a) {
 
 }  // namespace
 
-int fengine_pick_R(int L, int xprec, int n_in, int lds_limit) {
-    const int G = group_of(xprec);
-    const int L2 = l2_of(L);
-    // at least one FFT per lane per iteration, and about 8 KiB of output image
-    int R = (kThreads + G * L2 - 1) / (G * L2);
-    while (R * L * kRowBytes < 8192 && R < 64) R *= 2;
-    if (R > n_in) R = n_in;
-    if (R < 1) R = 1;
-    while (R > 1 && (fengine_lds_bytes(L, xprec, R, false) > lds_limit ||
-                     fengine_lds_bytes(L, xprec, R, true) > lds_limit))
-        R /= 2;
-    return R;
+template <int XP>
+static int cfg_value(int L, int what) {
+#define MWAX_CFG_CASE(LL)                                                                     \
+    case LL:                                                                                  \
+        return what == 0 ? FCfg<LL, XP>::R                                                    \
+                         : (what == 1 ? FCfg<LL, XP>::OUT_BYTES + FCfg<LL, XP>::STAGE_BYTES + \
+                                            FCfg<LL, XP>::EX_BYTES                            \
+                                      : std::max(FCfg<LL, XP>::STAGE_BYTES + FCfg<LL, XP>::EX_BYTES, \
+                                                 FCfg<LL, XP>::RED_BYTES));
+    switch (L) {
+        MWAX_CFG_CASE(1) MWAX_CFG_CASE(2) MWAX_CFG_CASE(4) MWAX_CFG_CASE(8) MWAX_CFG_CASE(16)
+        MWAX_CFG_CASE(32) MWAX_CFG_CASE(64) MWAX_CFG_CASE(128) MWAX_CFG_CASE(256)
+        MWAX_CFG_CASE(512) MWAX_CFG_CASE(1024)
+        default: return -1;
+    }
+#undef MWAX_CFG_CASE
+}
+
+static int cfg_of(int L, int xprec, int what) {
+    switch (xprec) {
+        case MWAX_X_INT8: return cfg_value<MWAX_X_INT8>(L, what);
+        case MWAX_X_FP16: return cfg_value<MWAX_X_FP16>(L, what);
+        default: return cfg_value<MWAX_X_FP32>(L, what);
+    }
 }
 
 int fengine_grid(int n_in, int R, int ngrp, bool stats) {
@@ -451,22 +529,9 @@ int fengine_grid(int n_in, int R, int ngrp, bool stats) {
     return (int)(items < cap ? items : cap);
 }
 
-int fengine_lds_bytes(int L, int xprec, int R, bool stats) {
-    const int G = group_of(xprec);
-    const int L2 = l2_of(L);
-    const int L1 = L / L2;
-    const int CP = R * kRowBytes + 16;
-    int bytes = stats ? 0 : L * CP;
-    if (L2 > 1) {
-        bytes += R * G * (2 * L + 16);
-        bytes += (kThreads / L2) * (L1 * (L2 + 1) + 8) * 8;
-    }
-    if (stats) {
-        const int red = kThreads * L1 * 4;
-        if (bytes < red) bytes = red;
-    }
-    return bytes;
-}
+int fengine_pick_R(int L, int xprec, int /*n_in*/, int /*lds_limit*/) { return cfg_of(L, xprec, 0); }
+
+int fengine_lds_bytes(int L, int xprec, int /*R*/, bool stats) { return cfg_of(L, xprec, stats ? 2 : 1); }
 
 hipError_t launch_fengine(int L, int xprec, const FArgs &a, hipStream_t s) {
     switch (xprec) {
@@ -484,8 +549,7 @@ hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s) {
 
 hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count, float *scales,
                                hipStream_t s) {
-    hipLaunchKernelGGL(calib_finish_kernel, dim3((L + 255) / 256), dim3(256), 0, s, stats, nwg, L,
-                       count, scales);
+    hipLaunchKernelGGL(calib_finish_kernel, dim3(L), dim3(256), 0, s, stats, nwg, L, count, scales);
     return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ template <>
 struct MfmaT<MWAX_X_FP16> {
     using acc_t = v16f;
     static constexpr int G = 8;
-    static constexpr int kFlushGroups = 1 << 30;  // only at the end of the segment
+    static constexpr int kFlushGroups = 8192;     // 65536 spectra per FP32 partial
     __device__ static acc_t mma(uint4 a, uint4 b, acc_t c) {
         v8h av, bv;
         __builtin_memcpy(&av, &a, 16);
@@ -95,149 +95,194 @@ struct MfmaT<MWAX_X_FP16> {
     }
 };
 
-template <int XP>
-__global__ __launch_bounds__(kThreads) void xengine_mfma(XArgs a) {
+// One workgroup = one channel x one 128 x 128 tile of the lower triangle.
+// Four waves in a 2 x 2 layout, 64 x 64 outputs (2 x 2 blocks of 32 x 32) each,
+// real and imaginary accumulators for every block (128 accumulator registers).
+// Two workgroups share a CU (two waves per SIMD), so one workgroup's barrier and
+// load latency is covered by the other's matrix work.  The K loop runs over
+// stages of kXG row groups, double-buffered in LDS: while the matrix cores work
+// on stage s, the next stage's global loads are in flight; one barrier per stage.
+// Accumulators are flushed into the integrators after each chunk of at most
+// kFlushGroups groups.
+constexpr int kXG = 2;                      // row groups per stage
+constexpr int kHalfPitch = kTile * 16 + 64; // LDS bytes per half of a group (padded)
+constexpr int kGroupPitch = 2 * kHalfPitch;
+constexpr int kPanel = kXG * kGroupPitch;   // one panel (A, B or B2) of a stage
+constexpr int kStage = 3 * kPanel;
+
+template <int XP, bool ACTIVE>
+__device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, int c, int rowA0, int rowB0,
+                                                  int wr, int wc) {
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
-    // LDS: three panels, each [kKG][2 halves][128 rows][16 B]
-    constexpr int kPanel = kKG * 2 * kTile * 16;
-    __shared__ __align__(16) uint8_t lds[3 * kPanel];
-    uint8_t *ldsA = lds, *ldsB = lds + kPanel, *ldsB2 = lds + 2 * kPanel;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int half = lane >> 5, l32 = lane & 31;
 
+    // staging: thread t owns row t/2, half t%2 of each group, for both panels
+    const int srow = tid >> 1, sh = tid & 1;
+    const bool okA = rowA0 + srow < a.n_in, okB = rowB0 + srow < a.n_in;
+    const int64_t gstride = (int64_t)a.n_in * kRowBytes;   // bytes between row groups
+    const uint8_t *base = a.chan + ((int64_t)c * a.NG + a.grp0) * gstride;
+    // Rows past the last input are loaded from a clamped (valid) address and not
+    // cleared: row i of A and column j of B reach only output (i, j), and outputs
+    // past the last input are never flushed.  Groups past the segment end must be
+    // zero; that test is uniform over the workgroup.
+    const uint8_t *pA = base + (int64_t)(okA ? rowA0 + srow : a.n_in - 1) * kRowBytes + sh * 16;
+    const uint8_t *pB = base + (int64_t)(okB ? rowB0 + srow : a.n_in - 1) * kRowBytes + sh * 16;
+    const int nstages = (a.ngrp + kXG - 1) / kXG;
+    const int lds_off = sh * kHalfPitch + srow * 16;
+    const int lds_off2 = (1 - sh) * kHalfPitch + srow * 16;
+
+    uint4 ra[kXG], rb[kXG];
+    auto load_stage = [&](int s) {
+#pragma unroll
+        for (int k = 0; k < kXG; ++k) {
+            const int g = s * kXG + k;
+            if (g < a.ngrp) {
+                const int64_t off = (int64_t)g * gstride;
+                ra[k] = *reinterpret_cast<const uint4 *>(pA + off);
+                rb[k] = *reinterpret_cast<const uint4 *>(pB + off);
+            } else {
+                ra[k] = make_uint4(0u, 0u, 0u, 0u);
+                rb[k] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+        uint8_t *st = lds + buf * kStage;
+#pragma unroll
+        for (int k = 0; k < kXG; ++k) {
+            const int ko = k * kGroupPitch;
+            *reinterpret_cast<uint4 *>(st + ko + lds_off) = ra[k];
+            *reinterpret_cast<uint4 *>(st + kPanel + ko + lds_off) = rb[k];
+            // B2 = [-im | re]: the re half goes to half 1, the negated im half to half 0
+            *reinterpret_cast<uint4 *>(st + 2 * kPanel + ko + lds_off2) = sh ? negate16<XP>(rb[k]) : rb[k];
+        }
+    };
+
+    acc_t re[2][2], im[2][2];
+    const int fa_off = half * kHalfPitch + (wr * 64 + l32) * 16;
+    const int fb_off = half * kHalfPitch + (wc * 64 + l32) * 16;
+
+    // One stage of matrix-core work from LDS buffer buf; the fragments of row
+    // group k+1 are read while the MFMAs of group k run.
+    auto compute = [&](int buf) {
+        const uint8_t *st = lds + buf * kStage;
+        uint4 fa[2][2], fb[2][2], fb2[2][2];
+        auto read = [&](int k, int slot) {
+            const int ko = k * kGroupPitch;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
+                fb[slot][m] = *reinterpret_cast<const uint4 *>(st + kPanel + ko + fb_off + m * 32 * 16);
+                fb2[slot][m] = *reinterpret_cast<const uint4 *>(st + 2 * kPanel + ko + fb_off + m * 32 * 16);
+            }
+        };
+        read(0, 0);
+#pragma unroll
+        for (int k = 0; k < kXG; ++k) {
+            if (k + 1 < kXG) read(k + 1, (k + 1) & 1);
+            const int sl = k & 1;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb2 = 0; nb2 < 2; ++nb2) {
+                    re[mb][nb2] = T::mma(fa[sl][mb], fb[sl][nb2], re[mb][nb2]);
+                    im[mb][nb2] = T::mma(fa[sl][mb], fb2[sl][nb2], im[mb][nb2]);
+                }
+        }
+        __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);         // reads, group 0
+#pragma unroll
+        for (int k = 0; k + 1 < kXG; ++k) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one read of group k+1
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
+    };
+
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    if (nstages > 1) load_stage(1);
+
+    for (int s0 = 0; s0 < nstages; s0 += T::kFlushGroups / kXG) {
+        const int s1 = min(nstages, s0 + T::kFlushGroups / kXG);
+        if constexpr (ACTIVE) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb2 = 0; nb2 < 2; ++nb2) {
+                    re[mb][nb2] = acc_t{};
+                    im[mb][nb2] = acc_t{};
+                }
+        }
+        for (int s = s0; s < s1; ++s) {
+            // stage s+1 is in registers (its loads were issued during stage s-1)
+            if constexpr (ACTIVE) compute(s & 1);
+            if (s + 1 < nstages) {
+                store_stage((s + 1) & 1);
+                if (s + 2 < nstages) load_stage(s + 2);
+            }
+            __syncthreads();
+        }
+        if constexpr (ACTIVE) {
+            // flush this chunk's partial sums into the integrators.  The base is made
+            // opaque here so the compiler cannot hoist 64 integrator addresses out of
+            // the K loop (they would occupy half the register file).
+            uint8_t *ibase = reinterpret_cast<uint8_t *>(a.integ);
+            int fr0 = rowA0, fc0 = rowB0;
+            asm volatile("" : "+s"(ibase), "+s"(fr0), "+s"(fc0));
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb2 = 0; nb2 < 2; ++nb2) {
+                    const int RB = wr * 2 + mb, CB = wc * 2 + nb2;
+                    const int n2 = fc0 + CB * 32 + l32;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int n1 = fr0 + RB * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
+                        if (n1 < a.n_in && n2 <= n1) {
+                            const int64_t p = (int64_t)n1 * (n1 + 1) / 2 + n2;
+                            if constexpr (XP == MWAX_X_INT8) {
+                                longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
+                                longlong2 v = *dst;
+                                v.x += re[mb][nb2][r];
+                                v.y += im[mb][nb2][r];
+                                *dst = v;
+                            } else {
+                                double2 *dst = reinterpret_cast<double2 *>(ibase) + (int64_t)c * a.P + p;
+                                double2 v = *dst;
+                                v.x += (double)re[mb][nb2][r];
+                                v.y += (double)im[mb][nb2][r];
+                                *dst = v;
+                            }
+                        }
+                    }
+                }
+        }
+    }
+}
+
+template <int XP>
+__global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
+    __shared__ __align__(16) uint8_t lds[2 * kStage];
     const int nb = gridDim.x;
     const int lin = xcd_logical(blockIdx.x, nb);
     const int c = lin / a.ntiles;
     int I, J;
     tile_ij(lin - c * a.ntiles, I, J);
     const int rowA0 = I * kTile, rowB0 = J * kTile;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wr = wave >> 1, wc = wave & 1;
-    const int half = lane >> 5, l32 = lane & 31;
-
-    // which 32 x 32 blocks this wave computes
-    bool act[2][2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb2 = 0; nb2 < 2; ++nb2) {
-            const int RB = wr * 2 + mb, CB = wc * 2 + nb2;
-            bool on = (rowA0 + RB * 32 < a.n_in) && (rowB0 + CB * 32 < a.n_in);
-            if (I == J && RB < CB) on = false;
-            act[mb][nb2] = on;
-        }
-    const bool any = act[0][0] || act[0][1] || act[1][0] || act[1][1];
-
-    acc_t re[2][2], im[2][2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb2 = 0; nb2 < 2; ++nb2) {
-            re[mb][nb2] = acc_t{};
-            im[mb][nb2] = acc_t{};
-        }
-
-    const uint8_t *base = a.chan + ((int64_t)c * a.NG + a.grp0) * (int64_t)a.n_in * kRowBytes;
-    const int64_t gstride = (int64_t)a.n_in * kRowBytes;   // bytes between row groups
-
-    // staging registers: kKG units of 16 B for each of the two panels
-    uint4 ra[kKG], rb[kKG];
-    auto load_stage = [&](int g0) {
-#pragma unroll
-        for (int k = 0; k < kKG; ++k) {
-            const int row = tid >> 1, h = tid & 1;
-            const bool gok = g0 + k < a.ngrp;
-            ra[k] = make_uint4(0, 0, 0, 0);
-            rb[k] = make_uint4(0, 0, 0, 0);
-            if (gok && rowA0 + row < a.n_in)
-                ra[k] = *reinterpret_cast<const uint4 *>(base + (g0 + k) * gstride + (int64_t)(rowA0 + row) * kRowBytes + h * 16);
-            if (gok && rowB0 + row < a.n_in)
-                rb[k] = *reinterpret_cast<const uint4 *>(base + (g0 + k) * gstride + (int64_t)(rowB0 + row) * kRowBytes + h * 16);
-        }
-    };
-    auto store_stage = [&]() {
-#pragma unroll
-        for (int k = 0; k < kKG; ++k) {
-            const int row = tid >> 1, h = tid & 1;
-            const int off = ((k * 2 + h) * kTile + row) * 16;
-            *reinterpret_cast<uint4 *>(ldsA + off) = ra[k];
-            *reinterpret_cast<uint4 *>(ldsB + off) = rb[k];
-            // B2 = [-im | re]: the re half goes to half 1, the negated im half to half 0
-            const int off2 = ((k * 2 + (1 - h)) * kTile + row) * 16;
-            *reinterpret_cast<uint4 *>(ldsB2 + off2) = h ? negate16<XP>(rb[k]) : rb[k];
-        }
-    };
-    auto flush = [&]() {
-        if (!any) return;
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int nb2 = 0; nb2 < 2; ++nb2) {
-                if (!act[mb][nb2]) continue;
-                const int n2 = rowB0 + (wc * 2 + nb2) * 32 + l32;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int n1 = rowA0 + (wr * 2 + mb) * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
-                    if (n1 < a.n_in && n2 <= n1) {
-                        const int64_t p = (int64_t)n1 * (n1 + 1) / 2 + n2;
-                        if constexpr (XP == MWAX_X_INT8) {
-                            longlong2 *dst = reinterpret_cast<longlong2 *>(a.integ) + (int64_t)c * a.P + p;
-                            longlong2 v = *dst;
-                            v.x += re[mb][nb2][r];
-                            v.y += im[mb][nb2][r];
-                            *dst = v;
-                        } else {
-                            double2 *dst = reinterpret_cast<double2 *>(a.integ) + (int64_t)c * a.P + p;
-                            double2 v = *dst;
-                            v.x += (double)re[mb][nb2][r];
-                            v.y += (double)im[mb][nb2][r];
-                            *dst = v;
-                        }
-                    }
-                }
-                re[mb][nb2] = acc_t{};
-                im[mb][nb2] = acc_t{};
-            }
-    };
-
-    int since_flush = 0;
-    load_stage(0);
-    for (int g0 = 0; g0 < a.ngrp; g0 += kKG) {
-        __syncthreads();
-        store_stage();
-        __syncthreads();
-        if (g0 + kKG < a.ngrp) load_stage(g0 + kKG);
-        if (any) {
-#pragma unroll
-            for (int k = 0; k < kKG; ++k) {
-                uint4 fa[2], fb[2], fb2[2];
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    fa[mb] = *reinterpret_cast<const uint4 *>(ldsA + ((k * 2 + half) * kTile + wr * 64 + mb * 32 + l32) * 16);
-#pragma unroll
-                for (int nb2 = 0; nb2 < 2; ++nb2) {
-                    const int off = ((k * 2 + half) * kTile + wc * 64 + nb2 * 32 + l32) * 16;
-                    fb[nb2] = *reinterpret_cast<const uint4 *>(ldsB + off);
-                    fb2[nb2] = *reinterpret_cast<const uint4 *>(ldsB2 + off);
-                }
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                    for (int nb2 = 0; nb2 < 2; ++nb2) {
-                        // blocks of an active wave are all computed (a wave's time is set by
-                        // its busiest sibling anyway); inactive ones are dropped at flush
-                        re[mb][nb2] = T::mma(fa[mb], fb[nb2], re[mb][nb2]);
-                        im[mb][nb2] = T::mma(fa[mb], fb2[nb2], im[mb][nb2]);
-                    }
-            }
-        }
-        since_flush += kKG;
-        if (since_flush >= T::kFlushGroups) {
-            flush();
-            since_flush = 0;
-        }
-    }
-    if (since_flush > 0) flush();
+    // A wave is idle on a diagonal tile above the diagonal, or when all its rows or
+    // columns lie past the last input; it still stages data and meets the barriers.
+    const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
+    if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
+    else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
 }
 
 // ---------------------------------------------------------------------------
