@@ -17,7 +17,6 @@ FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,19 +33,65 @@ PEAK = {  # MI355X published dense peaks
 }
 N_TILES, L, SECONDS, F_S = 256, 128, 8.0, 1.28e6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
-KERNEL_SOURCES = {
-    "xengine": os.path.join(ROOT, "paper_2303_11557_amd", "csrc", "xengine.hip"),
-    "fengine": os.path.join(ROOT, "paper_2303_11557_amd", "csrc", "fengine.hip"),
-}
 
 
-def source_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def measured_traffic(key):
+    """HBM bytes per launch of kernel `key` from the committed counter summary, or
+    None when there is none or the kernel's source has changed since it was taken."""
+    from paper_2303_11557_amd import profiling
+    try:
+        ent = json.load(open(TRAFFIC_FILE)).get(key)
+    except (OSError, ValueError):
+        return None
+    if not ent or ent.get("source_sha") != profiling.source_sha(key.split("_")[0]):
+        return None
+    return ent["hbm_bytes_per_launch"]
+
+
+# Batch workload: 24 coarse channels as uneven instances (tile counts, FFT
+# lengths, integration times cycled), each with 8 s of sigma = 8 voltages and
+# one seeded point source; run as one batch in 1 s calls.
+C4_TILES, C4_L, C4_TAU = (64, 128, 256), (32, 128, 1024), (0.5, 2.0, 8.0)
+C4_CHUNK_S = 1.0
+
+
+def c4_instances():
+    return [(C4_TILES[i % 3], C4_L[(i // 3) % 3], C4_TAU[(i // 9) % 3]) for i in range(24)]
+
+
+def cpu_baseline(volts, L, seconds, what):
+    """The FP64 oracle (channelise + packed-triangle X-engine) timed on the host
+    cores over the first spectra of ``volts`` (a device int8 [n][S][2] tensor),
+    the sample grown until it takes about ``seconds``."""
+    import oracle
+    n_in = volts.shape[0]
+    P = n_in * (n_in + 1) // 2
+    threads = max(1, min(16, os.cpu_count() or 1))
+    max_spec = min(2048, volts.shape[1] // L)
+    v_host = volts[:, : max_spec * L].cpu().numpy()
+
+    def oracle_rate(n_spec):
+        t0 = time.perf_counter()
+        spec = oracle.channelise(v_host, L, nm=n_spec)
+        oracle.correlate(spec, n_spec, threads=threads)
+        return time.perf_counter() - t0
+
+    n_spec = 4
+    dt = oracle_rate(n_spec)
+    while dt < 0.5 * seconds and n_spec < max_spec:
+        n_spec = int(min(max_spec, max(2 * n_spec, n_spec * seconds / max(dt, 1e-3))))
+        dt = oracle_rate(n_spec)
+    return {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
+                      f"({n_spec * L} samples) of {what}; FP64 FFT + packed triangle; {dt:.1f} s wall"}
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
+                    help="c3: one coarse channel, 256 tiles, 8 s (the headline metric); "
+                         "c4: 24 uneven instances as one batch")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--xprec", default="int8", choices=["int8", "fp16", "fp32"])
@@ -60,6 +105,105 @@ def parse():
     return ap.parse_args()
 
 
+def main_c4(args):
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+    from paper_2303_11557_amd.mwax import Batch, make_config
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    S = int(SECONDS * F_S)
+    chunk = int(C4_CHUNK_S * F_S)
+    ncalls = S // chunk
+    inst = c4_instances()
+    cfgs = [make_config(t, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=chunk) for (t, Lc, tau) in inst]
+    dims = [mwax.derive(c) for c in cfgs]
+    cmac_per_step = sum(d.n_pairs * S for d in dims)
+    volts = []
+    for i, (t, Lc, tau) in enumerate(inst):
+        v = torch.empty((2 * t, S, 2), dtype=torch.int8, device="cuda")
+        synth.device_volts(v, seed=synth.MWAX_SEED + 3 + (i << 16),
+                           sources=[synth.Source(3.0, (7 * i) % Lc - Lc // 2)], L=Lc)
+        volts.append(v)
+    torch.cuda.synchronize()
+    outs = [torch.empty((-(-chunk // (d.spectra_per_int * d.fft_len)) + 1, d.fft_len, d.n_pairs),
+                        dtype=torch.complex64, device="cuda") for d in dims]
+
+    with Batch(cfgs) as b:
+        t0 = time.perf_counter()
+        kc, grid = b.autotune([v[:, :chunk] for v in volts], trials=3)
+        tune_s = time.perf_counter() - t0
+
+        def step():
+            for k in range(ncalls):
+                b.run([v[:, k * chunk:(k + 1) * chunk] for v in volts])
+                for i, p in enumerate(b.plans):
+                    p.integrate(outs[i].shape[0], out=outs[i])
+
+        for _ in range(args.warmup):
+            step()
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        b.sync()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        # one more pass with the launches issued one by one, for per-kernel times
+        b.set_graph(False)
+        b.set_timing(True)
+        for fam in range(5):
+            b.kernel_time(fam)
+        step()
+        fam = {name: b.kernel_time(i) for i, name in
+               ((0, "fengine"), (1, "xengine"), (3, "calib"), (4, "call"))}
+        b.set_timing(False)
+        b.set_graph(True)
+        eager_ms = fam["call"][0]
+
+    x_ms, x_n = fam["xengine"]
+    x_ops_launch = 8.0 * cmac_per_step / max(x_n, 1)
+    x_avg = x_ms / max(x_n, 1)
+    x_ach = x_ops_launch / (x_avg / 1e3) / 1e12
+    x_peak = PEAK["int8_tops"] if args.xprec == "int8" else PEAK["fp16_tflops"]
+    b_out = 2 if args.xprec == "int8" else 4
+    f_ms, f_n = fam["fengine"]
+    f_bytes = sum(d.n_inputs * S * (2 + b_out) for d in dims)
+    f_gbs = f_bytes / (f_ms / 1e3) / 1e9
+    roof_x = {"kernel": f"xengine_batch_{args.xprec}", "bound": "mfma", "achieved": round(x_ach, 2),
+              "peak": x_peak, "unit": "TFLOP/s", "frac": round(x_ach / x_peak, 4), "traffic": None,
+              "avg_launch_ms": round(x_avg, 4), "launches": x_n, "ops_per_launch": x_ops_launch}
+    roof_f = {"kernel": f"fengine_batch_{args.xprec}", "bound": "hbm", "achieved": round(f_gbs, 1),
+              "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(f_gbs / PEAK["hbm_gbs"], 4),
+              "traffic": None, "ms_per_step": round(f_ms, 3), "launches": f_n, "bytes_per_step": f_bytes}
+    dominant, other = (roof_x, roof_f) if x_ms >= f_ms else (roof_f, roof_x)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(volts[2], C4_L[0], args.cpu_seconds,
+                                                         "instance 2 (256 tiles, 32-pt FFT)")
+    line = {
+        "metric": "X-engine CMAC/s & real-time factor, 24 uneven instances in one batch",
+        "value": cmac_per_step / (ms / 1e3), "unit": "CMAC/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.xprec,
+        "data": "synthetic",
+        "config": {"workload": "24 instances: tiles {64,128,256} x 2 pols, FFT {32,128,1024}, integrations "
+                               "{0.5,2,8} s (cycled), 8 s of complex int8 sigma=8 voltages + 1 source each, "
+                               "one batch, 1 s calls",
+                   "instances": [list(x) for x in inst], "cmac_per_step": cmac_per_step,
+                   "input_bytes": sum(v.numel() for v in volts)},
+        "rtf": round(SECONDS / (ms / 1e3), 2),
+        "graph_replay": True,
+        "eager_ms_per_step": round(eager_ms, 3),
+        "calibration_ms_per_step": round(fam["calib"][0], 3),
+        "autotune": {"kchunk": kc, "grid": grid, "seconds": round(tune_s, 2)},
+        "roofline": dominant, "roofline_other": other,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -67,7 +211,9 @@ def main():
               "(coarse channels shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.workload == "c4":
+        return main_c4(args)
+
     import torch
 
     import synth
@@ -106,7 +252,7 @@ def main():
                 step()
             p.sync()
             p.set_timing(True)
-            for fam in (0, 1, 2):
+            for fam in range(4):
                 p.kernel_time(fam)               # clear
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -115,7 +261,7 @@ def main():
             p.sync()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            fam = {name: p.kernel_time(i) for i, name in enumerate(("fengine", "xengine", "pack"))}
+            fam = {name: p.kernel_time(i) for i, name in enumerate(("fengine", "xengine", "pack", "calib"))}
             p.set_timing(False)
         ms = (t1 - t0) * 1e3 / steps
         return ms, fam, out
@@ -133,30 +279,24 @@ def main():
     x_ops_launch = 8.0 * cmac_per_step * args.steps / max(x_n, 1)
     x_avg_ms = x_ms / max(x_n, 1)
     x_achieved = x_ops_launch / (x_avg_ms / 1e3) / 1e12
-    # F-engine: int8 in + channelised out per sample of every input (main pass; the
-    # calibration pass over the first 1024 spectra of each integration is counted in
-    # the F-engine time, not in its bytes)
-    f_bytes_step = n_in * S * (2 + b_out)
-    f_gbs = f_bytes_step * args.steps / (f_ms / 1e3) / 1e9 if f_ms > 0 else 0.0
-
-    traffic = None
-    try:
-        tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get(f"xengine_{args.xprec}")
-        if ent and ent.get("source_sha") == source_hash(KERNEL_SOURCES["xengine"]):
-            traffic = ent["hbm_bytes_per_launch"]
-    except (OSError, ValueError):
-        pass
+    # F-engine main pass: int8 in + channelised out per sample of every input.  The
+    # int8 scale calibration (a statistics pass over the first 1024 spectra of each
+    # integration and its reduction) is timed and reported on its own.
+    f_bytes_launch = n_in * S * (2 + b_out) * args.steps / max(f_n, 1)
+    f_avg_ms = f_ms / max(f_n, 1)
+    f_gbs = f_bytes_launch / (f_avg_ms / 1e3) / 1e9 if f_ms > 0 else 0.0
+    c_ms, _ = fam["calib"]
 
     roof_x = {"kernel": f"xengine_{args.xprec}", "bound": "mfma" if args.xprec != "fp32" else "alu",
               "achieved": round(x_achieved, 2), "peak": x_peak, "unit": "TFLOP/s",
-              "frac": round(x_achieved / x_peak, 4), "traffic": traffic,
+              "frac": round(x_achieved / x_peak, 4), "traffic": measured_traffic(f"xengine_{args.xprec}"),
               "avg_launch_ms": round(x_avg_ms, 4), "launches": x_n,
               "ops_per_launch": x_ops_launch}
     roof_f = {"kernel": f"fengine_{args.xprec}", "bound": "hbm", "achieved": round(f_gbs, 1),
               "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(f_gbs / PEAK["hbm_gbs"], 4),
-              "traffic": None, "time_ms_per_step": round(f_ms / args.steps, 4),
-              "bytes_per_step": f_bytes_step}
+              "traffic": measured_traffic(f"fengine_{args.xprec}"),
+              "avg_launch_ms": round(f_avg_ms, 4), "launches": f_n,
+              "bytes_per_launch": f_bytes_launch}
     dominant, other = (roof_x, roof_f) if x_ms >= f_ms else (roof_f, roof_x)
 
     # ---- other X-engine precisions on the same block
@@ -179,28 +319,8 @@ def main():
             variants["speedup_vs_fp32_plain"] = round(variants["fp32"]["ms_per_step"] / ms, 2)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same block
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
-        max_spec = 2048
-        v_host = volts[:, : max_spec * L].cpu().numpy()
-
-        def oracle_rate(n_spec):
-            t0 = time.perf_counter()
-            spec = oracle.channelise(v_host, L, nm=n_spec)
-            oracle.correlate(spec, n_spec, threads=threads)
-            return time.perf_counter() - t0
-
-        n_spec = 4
-        dt = oracle_rate(n_spec)
-        while dt < 0.5 * args.cpu_seconds and n_spec < max_spec:
-            n_spec = int(min(max_spec, max(2 * n_spec, n_spec * args.cpu_seconds / max(dt, 1e-3))))
-            dt = oracle_rate(n_spec)
-        cpu = {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
-               "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
-                         f"({n_spec * L} samples) of the same 8 s block; FP64 FFT + packed triangle; "
-                         f"{dt:.1f} s wall"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(volts, L, args.cpu_seconds,
+                                                         "the same 8 s block")
 
     rtf = SECONDS / (ms / 1e3)
     line = {
@@ -228,6 +348,7 @@ def main():
         "roofline": dominant,
         "roofline_other": other,
         "pack_ms_per_step": round(p_ms / max(args.steps, 1), 4),
+        "calibration_ms_per_step": round(c_ms / max(args.steps, 1), 4),
         "variants": variants,
         "cpu_baseline": cpu,
     }

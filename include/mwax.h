@@ -206,11 +206,87 @@ mwax_status mwax_sync(mwax_plan p);
 /* Kernel timing for measurement.  When enabled, the plan records HIP events on
  * its stream around each launch of the F-engine, X-engine and pack kernels.
  * mwax_kernel_time synchronises the stream and returns, for a kernel family
- * (0 = F-engine incl. calibration, 1 = X-engine, 2 = pack), the summed
- * duration in milliseconds and the launch count since the last read, then
- * clears them. */
+ * (0 = F-engine main pass, 1 = X-engine, 2 = pack, 3 = int8 scale
+ * calibration: statistics pass and its reduction), the summed duration in
+ * milliseconds and the launch count since the last read, then clears them. */
 mwax_status mwax_set_timing(mwax_plan p, int32_t enable);
 mwax_status mwax_kernel_time(mwax_plan p, int32_t family, double *total_ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Batches.  The cluster of Sec. 2.1 correlates up to 24 coarse channels, one
+ * per server, each with the FX engine of Sec. 2.5.  A batch runs many such
+ * per-coarse-channel plans ("instances", which may differ in tile count, FFT
+ * length and integration time) on one GPU as one unit of device work per call:
+ * the table-driven F-engine launches (one per distinct FFT length), the scale
+ * calibration and a single persistent matrix-core X-engine launch that takes
+ * 128 x 128 tiles of every instance from per-XCD work queues.  The sequence is
+ * captured once in a HIP graph and replayed on every call; only its device
+ * work tables change (uploaded from pinned host memory ahead of the replay).
+ *
+ * Each instance is a full plan (same workspace, stream position, integrators
+ * and mwax_integrate / mwax_integrate_raw_i64 / mwax_plan_get_dims /
+ * mwax_set_scales behaviour); the batch owns them.  Results are those of the
+ * same plans driven one by one with mwax_channelise + mwax_correlate: bit for
+ * bit for INT8, and for FP16 too (every integrator element is summed in the
+ * same order).
+ * ------------------------------------------------------------------------ */
+typedef struct mwax_batch_s *mwax_batch;
+
+/* Create a batch of n (1..64) instances from cfgs[n].  All instances must use
+ * the same xprec, INT8 or FP16 (FP32 runs on the vector ALUs and is not
+ * batched: MWAX_E_UNSUPPORTED).  hip_stream: the stream every batch call
+ * enqueues on; NULL makes the batch create its own stream, which like the
+ * default stream's other users synchronises with the legacy default stream.
+ * Errors: MWAX_E_INVAL (a configuration, with its index in the message),
+ * MWAX_E_UNSUPPORTED, MWAX_E_NOMEM, MWAX_E_DEVICE. */
+mwax_status mwax_batch_create(const mwax_config *cfgs, int32_t n, void *hip_stream, mwax_batch *out);
+
+/* Release the batch, its instances and its tables (waits for its stream). */
+mwax_status mwax_batch_destroy(mwax_batch b);
+
+/* Instance i's plan handle, for mwax_integrate and the other per-plan calls.
+ * It stays owned by the batch: mwax_plan_destroy on it is refused. */
+mwax_status mwax_batch_plan(mwax_batch b, int32_t i, mwax_plan *out);
+
+/* One batch step: for every instance i with n_samples[i] > 0, the work of
+ * mwax_channelise(plan_i, d_volts[i], n_samples[i], ld_samples[i]) followed by
+ * mwax_correlate(plan_i); instances with n_samples[i] == 0 are left as they
+ * are.  d_volts, n_samples and ld_samples are host arrays of n entries (the
+ * voltage pointers are device pointers, rules as in mwax_channelise).  All
+ * arguments and states are checked first: on any error nothing is enqueued
+ * and no instance changes. */
+mwax_status mwax_batch_run(mwax_batch b, const int8_t *const *d_volts, const int64_t *n_samples,
+                           const int64_t *ld_samples);
+
+/* Autotuner: on the given block (as for mwax_batch_run, every n_samples[i] >
+ * 0), channelise once, then time the persistent X-engine on the device for
+ * candidate work shapes: per instance shape (inputs, L), the number of row
+ * groups per work item (whole segments, or chunks of 4096 .. 128 row groups;
+ * INT8 only, chunks of one tile then flush with exact int64 atomic adds), and
+ * the persistent grid size.  Each candidate is timed `trials` times (median);
+ * the fastest is kept.  Needs every instance at stream position 0 with nothing
+ * accumulated (MWAX_E_STATE otherwise) and resets every instance afterwards. */
+mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, const int64_t *n_samples,
+                                const int64_t *ld_samples, int32_t trials);
+
+/* The tuning in force: kchunk[n] row groups per work item (0 = whole segment)
+ * and the persistent X-engine grid.  set_tuning installs one (kchunk must be
+ * 0, or >= 1 for INT8 batches; grid 0 = the device's resident maximum). */
+mwax_status mwax_batch_get_tuning(mwax_batch b, int32_t *kchunk, int32_t *grid);
+mwax_status mwax_batch_set_tuning(mwax_batch b, const int32_t *kchunk, int32_t grid);
+
+/* Graph replay on (1, the default) or off (0: the same launches issued one by
+ * one, which also allows per-kernel timing). */
+mwax_status mwax_batch_set_graph(mwax_batch b, int32_t enable);
+
+/* Timing as mwax_set_timing / mwax_kernel_time, per batch: families 0 =
+ * F-engine main pass, 1 = X-engine, 3 = calibration (graph off only), 4 =
+ * whole batch step (both modes). */
+mwax_status mwax_batch_set_timing(mwax_batch b, int32_t enable);
+mwax_status mwax_batch_kernel_time(mwax_batch b, int32_t family, double *total_ms, int64_t *launches);
+
+/* Wait for the batch's stream. */
+mwax_status mwax_batch_sync(mwax_batch b);
 
 /* Message for the last error of the calling thread (empty if none). */
 const char *mwax_last_error(void);

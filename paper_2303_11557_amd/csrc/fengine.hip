@@ -161,12 +161,12 @@ __device__ __forceinline__ float2 load_pair_biased(const uint8_t *p) {
     return make_float2((float)(w & 0xffu), (float)((w >> 8) & 0xffu));
 }
 
+// The work of workgroup wg of nwg workgroups on the segment described by a.
 template <int L, int XP, bool STATS>
-__global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
+__device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const int nwg, uint8_t *smem) {
     using C = FCfg<L, XP>;
     constexpr int L1 = C::L1, L2 = C::L2, U = C::U, G = C::G, ES = C::ES, FPG = C::FPG;
     constexpr int GPW = C::GPW, PACKS = C::PACKS, R = C::R, CP = C::CP, SP = C::SP, EXG = C::EXG;
-    extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *outbuf = smem;
     uint8_t *stage = smem + (STATS ? 0 : C::OUT_BYTES);
     float2 *ex = reinterpret_cast<float2 *>(stage + C::STAGE_BYTES);
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
     for (int i = 0; i < (STATS ? L1 : 1); ++i) acc[i] = 0.0f;
     const float bias = 128.0f * (float)L;      // DC offset of the biased input
 
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    for (int item = wg; item < items; item += nwg) {
         const int gsel = item / nblk;
         const int n0 = (item - gsel * nblk) * R;
         const int nrows = min(R, a.n_in - n0);
@@ -362,9 +362,36 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
             const int rr = t / L1, i = t - rr * L1;
             double sum = 0.0;
             for (int sl = 0; sl < NSLOT; ++sl) sum += (double)red[(sl * L2 + rr) * L1 + i];
-            a.stats[(int64_t)blockIdx.x * L + chan_of<L>(rr, i)] = sum;
+            a.stats[(int64_t)wg * L + chan_of<L>(rr, i)] = sum;
         }
     }
+}
+
+template <int L, int XP, bool STATS>
+__global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    fengine_body<L, XP, STATS>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Batched form: workgroups [block0[d], block0[d+1]) of the launch work on
+// descriptor d (a segment of one plan of the batch); the rest return at once.
+template <int L, int XP, bool STATS>
+__global__ __launch_bounds__(kThreads) void fengine_batch_kernel(FBatchArgs b) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int nd = *b.ndesc;
+    const int blk = blockIdx.x;
+    if (blk >= b.block0[nd]) return;
+    int d = 0;
+    while (b.block0[d + 1] <= blk) ++d;
+    const FArgs a = b.desc[d];
+    fengine_body<L, XP, STATS>(a, blk - b.block0[d], b.block0[d + 1] - b.block0[d], smem);
+}
+
+template <int L, int XP>
+constexpr int cfg_value_lds(bool stats) {
+    using C = FCfg<L, XP>;
+    return stats ? (C::STAGE_BYTES + C::EX_BYTES > C::RED_BYTES ? C::STAGE_BYTES + C::EX_BYTES : C::RED_BYTES)
+                 : C::OUT_BYTES + C::STAGE_BYTES + C::EX_BYTES;
 }
 
 template <int L, int XP>
@@ -388,6 +415,56 @@ hipError_t launch_L(const FArgs &a, hipStream_t s) {
     else
         hipLaunchKernelGGL((fengine_kernel<L, XP, false>), dim3((unsigned)grid), dim3(kThreads), lds, s, a);
     return hipGetLastError();
+}
+
+template <int L, int XP>
+hipError_t prepare_batch_L() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fengine_batch_kernel<L, XP, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fengine_batch_kernel<L, XP, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    return e;
+}
+
+template <int L, int XP>
+hipError_t launch_batch_L(bool stats, const FBatchArgs &b, int grid, hipStream_t s) {
+    const int lds = cfg_value_lds<L, XP>(stats);
+    if (stats)
+        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, true>), dim3((unsigned)grid), dim3(kThreads), lds, s, b);
+    else
+        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, false>), dim3((unsigned)grid), dim3(kThreads), lds, s, b);
+    return hipGetLastError();
+}
+
+#define MWAX_L_SWITCH(CALL)                         \
+    switch (L) {                                    \
+        case 1: return CALL(1);                     \
+        case 2: return CALL(2);                     \
+        case 4: return CALL(4);                     \
+        case 8: return CALL(8);                     \
+        case 16: return CALL(16);                   \
+        case 32: return CALL(32);                   \
+        case 64: return CALL(64);                   \
+        case 128: return CALL(128);                 \
+        case 256: return CALL(256);                 \
+        case 512: return CALL(512);                 \
+        case 1024: return CALL(1024);               \
+        default: return hipErrorInvalidValue;       \
+    }
+
+template <int XP>
+hipError_t launch_batch_xp(int L, bool stats, const FBatchArgs &b, int grid, hipStream_t s) {
+#define MWAX_CALL(LL) launch_batch_L<LL, XP>(stats, b, grid, s)
+    MWAX_L_SWITCH(MWAX_CALL)
+#undef MWAX_CALL
+}
+
+template <int XP>
+hipError_t prepare_batch_xp(int L) {
+#define MWAX_CALL(LL) prepare_batch_L<LL, XP>()
+    MWAX_L_SWITCH(MWAX_CALL)
+#undef MWAX_CALL
 }
 
 template <int XP>
@@ -431,9 +508,10 @@ __global__ void twiddle_kernel(float2 *tw, int L) {
 
 // One workgroup per channel: threads sum strided partial rows, then a fixed-order
 // tree in LDS, so the result does not depend on scheduling.
-__global__ void calib_finish_kernel(const double *stats, int nwg, int L, double count, float *scales) {
+// Scale of channel c from the partial power sums of nwg workgroups, reduced in a
+// fixed order (bitwise reproducible).
+__device__ void calib_finish_channel(const double *stats, int nwg, int L, double count, float *scales, int c) {
     __shared__ double part[256];
-    const int c = blockIdx.x;
     double t = 0.0;
     for (int w = threadIdx.x; w < nwg; w += 256) t += stats[(int64_t)w * L + c];
     part[threadIdx.x] = t;
@@ -452,6 +530,27 @@ __global__ void calib_finish_kernel(const double *stats, int nwg, int L, double 
     }
     scales[c] = s;
     scales[L + c] = inv;
+}
+
+__global__ void calib_finish_kernel(const double *stats, int nwg, int L, double count, float *scales) {
+    calib_finish_channel(stats, nwg, L, count, scales, blockIdx.x);
+}
+
+// One workgroup per (channel, descriptor); descriptors past *ndesc and channels
+// past the descriptor's L return at once.
+__global__ void calib_batch_kernel(const CalDesc *desc, const int32_t *ndesc) {
+    const int d = blockIdx.y, c = blockIdx.x;
+    if (d >= *ndesc) return;
+    const CalDesc cd = desc[d];
+    if (c >= cd.L) return;
+    if (cd.copy_src) {
+        if (threadIdx.x == 0) {
+            cd.scales[c] = cd.copy_src[c];
+            cd.scales[cd.L + c] = cd.copy_src[cd.L + c];
+        }
+        return;
+    }
+    calib_finish_channel(cd.stats, cd.nwg, cd.L, cd.count, cd.scales, c);
 }
 
 __global__ void copy_scales_kernel(const float *src, float *dst, int n) {
@@ -540,6 +639,31 @@ hipError_t launch_fengine(int L, int xprec, const FArgs &a, hipStream_t s) {
         case MWAX_X_FP32: return launch_xp<MWAX_X_FP32>(L, a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_fengine_batch(int L, int xprec, bool stats, const FBatchArgs &b, int grid, hipStream_t s) {
+    if (grid < 1) return hipSuccess;
+    switch (xprec) {
+        case MWAX_X_INT8: return launch_batch_xp<MWAX_X_INT8>(L, stats, b, grid, s);
+        case MWAX_X_FP16: return launch_batch_xp<MWAX_X_FP16>(L, stats, b, grid, s);
+        case MWAX_X_FP32: return launch_batch_xp<MWAX_X_FP32>(L, stats, b, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fengine_prepare_batch(int L, int xprec) {
+    switch (xprec) {
+        case MWAX_X_INT8: return prepare_batch_xp<MWAX_X_INT8>(L);
+        case MWAX_X_FP16: return prepare_batch_xp<MWAX_X_FP16>(L);
+        case MWAX_X_FP32: return prepare_batch_xp<MWAX_X_FP32>(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_calib_batch(const CalDesc *desc, const int32_t *ndesc, int max_desc, int max_L, hipStream_t s) {
+    if (max_desc < 1) return hipSuccess;
+    hipLaunchKernelGGL(calib_batch_kernel, dim3((unsigned)max_L, (unsigned)max_desc), dim3(256), 0, s, desc, ndesc);
+    return hipGetLastError();
 }
 
 hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s) {

@@ -59,6 +59,29 @@ hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count
                                hipStream_t s);
 hipError_t launch_copy_scales(const float *src, float *dst, int L, hipStream_t s);
 
+// Batched F-engine: one launch covers the segments of many plans with the same
+// L and precision.  The tables live in device memory (they change per call while
+// the launch itself, grid included, is fixed and can be replayed from a graph).
+struct FBatchArgs {
+    const FArgs *desc;      // [ndesc] segments
+    const int32_t *block0;  // [ndesc + 1] first workgroup of each descriptor
+    const int32_t *ndesc;   // number of descriptors this call
+};
+hipError_t launch_fengine_batch(int L, int xprec, bool stats, const FBatchArgs &b, int grid, hipStream_t s);
+hipError_t fengine_prepare_batch(int L, int xprec);   // LDS attribute, once, outside graph capture
+
+// Batched scale calibration finish (or copy of fixed scales), one descriptor per
+// integration that begins in the call.
+struct CalDesc {
+    const double *stats;    // [nwg][L] partial power sums (NULL in copy mode)
+    const float *copy_src;  // copy mode: [2][L] scales to install
+    float *scales;          // [2][L] destination (s, inv_s)
+    double count;           // inputs x spectra of the calibration window
+    int32_t nwg;
+    int32_t L;
+};
+hipError_t launch_calib_batch(const CalDesc *desc, const int32_t *ndesc, int max_desc, int max_L, hipStream_t s);
+
 // Canonical [M][L][N_in][2] <-> internal layout, one segment at a time.
 struct RepackArgs {
     void *canon;            // [M][L][N_in][2] elements
@@ -88,6 +111,43 @@ struct XArgs {
 };
 hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s);
 int xengine_tile(int xprec);
+
+// Persistent batched X-engine.  A work item is one 128 x 128 tile of one channel
+// of one segment over a chunk of its row groups, packed in 32 bits:
+//   desc (8 bits) | channel (10) | tile (8) | chunk (6)
+// Items sit in 8 queues, one per XCD (workgroup b runs on XCD b mod 8); a
+// workgroup drains its own queue, then takes work from the others.  Chunks of
+// one (channel, tile) run concurrently only in segments with ksplit > 1, whose
+// flushes are int64 atomic adds (exact and order-free); otherwise every
+// integrator element has one writer per launch.
+struct XDesc {
+    const uint8_t *chan;
+    int64_t NG;
+    int64_t grp0;
+    void *integ;            // segment's slot integrators [L][P][2]
+    int64_t P;
+    int32_t ngrp;           // row groups of the segment
+    int32_t n_in;
+    int32_t kchunk;         // row groups per chunk
+    int32_t ksplit;         // chunks = ceil(ngrp / kchunk)
+};
+constexpr int kXBatchMaxDesc = 256;
+constexpr int kXBatchMaxTiles = 256;
+constexpr int kXBatchMaxSplit = 64;
+constexpr int kXQueues = 8;
+constexpr int kXCounterStride = 64;   // ints between queue counters (256 bytes)
+__host__ __device__ inline uint32_t xitem_pack(int d, int c, int t, int k) {
+    return ((uint32_t)d << 24) | ((uint32_t)c << 14) | ((uint32_t)t << 6) | (uint32_t)k;
+}
+struct XBatchArgs {
+    const XDesc *desc;
+    const uint32_t *items;  // queue q holds items[qbeg[q] .. qbeg[q+1])
+    const int32_t *qbeg;    // [kXQueues + 1]
+    int32_t *counters;      // [kXQueues * kXCounterStride], zero at launch
+};
+hipError_t launch_xengine_batch(int xprec, const XBatchArgs &b, int grid, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
+int xengine_batch_max_grid(int xprec, int device);   // resident workgroups on the device
 
 // ---------------------------------------------------------------------------
 // Integrate / pack

@@ -1,0 +1,106 @@
+// Host-side state of a plan, shared by the single-plan and batch runtimes of
+// libmwax (not part of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "mwax_internal.h"
+
+namespace mwax {
+
+// Error reporting: set the calling thread's last-error message and return s.
+mwax_status fail(mwax_status s, const char *fmt, ...);
+mwax_status ok();
+mwax_status hip_fail(hipError_t e, const char *what);
+
+constexpr int64_t kCalSamples = 131072;   // calibration window: 0.1024 s at 1.28 Msps
+
+struct Segment {
+    int64_t j;        // integration index
+    int slot;         // device slot
+    int64_t frame0;   // first spectrum of the segment within the call
+    int64_t nframes;  // spectra in the segment
+    int64_t grp0;     // first row group in the channel-major buffer
+    int64_t ngrp;     // row groups
+    int64_t local0;   // offset of the first spectrum within integration j
+};
+
+}  // namespace mwax
+
+struct mwax_plan_s {
+    mwax_config cfg{};
+    mwax_dims d{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int L = 0, G = 0, n_in = 0, xprec = 0, R = 1, ntiles = 0;
+    int64_t T = 0, P = 0;
+
+    uint8_t *chan = nullptr;
+    int64_t NG = 0;
+    void *integ = nullptr;
+    size_t slot_bytes = 0;
+    int nslots = 0;
+    float *scales = nullptr;        // [nslots][2][L] (s, inv_s)
+    float *fixed = nullptr;         // [2][L] user scales
+    float *ones = nullptr;          // [2][L] = 1
+    float2 *tw = nullptr;
+    double *stats = nullptr;        // [kStatsMaxWG][L]
+
+    int64_t g_chan = 0;             // stream spectra channelised (incl. the pending block)
+    bool pending = false;           // a channelised block awaits mwax_correlate
+    bool have_block = false;        // the buffer holds a block (for read-back)
+    int64_t block_spectra = 0;
+    std::vector<mwax::Segment> segs;
+    std::vector<int64_t> slot_owner, slot_count;
+    int64_t next_emit = 0;
+    bool fixed_mode = false;
+    bool in_batch = false;          // owned by a batch (destroyed with it)
+
+    bool timing = false;
+    struct Ev { hipEvent_t a, b; int fam; };
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> pool;
+    double t_ms[4] = {0, 0, 0, 0};
+    int64_t t_n[4] = {0, 0, 0, 0};
+};
+
+namespace mwax {
+
+inline hipEvent_t get_event(mwax_plan p) {
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Wraps a launch with timing events when timing is on.
+template <class F>
+hipError_t timed(mwax_plan p, int fam, F &&launch) {
+    if (!p->timing) return launch();
+    hipEvent_t a = get_event(p), b = get_event(p);
+    if (!a || !b) return hipErrorOutOfMemory;
+    (void)hipEventRecord(a, p->stream);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, p->stream);
+    p->events.push_back({a, b, fam});
+    return e;
+}
+
+mwax_status derive(const mwax_config *cfg, mwax_dims *o);
+void free_plan(mwax_plan p);
+// Split a block of M spectra at integration boundaries and check slot use.
+mwax_status plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out);
+// Per-integration scale calibration launch arguments of a segment that begins an
+// integration (INT8, automatic scales).
+FArgs calib_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld);
+// F-engine main-pass launch arguments of a segment.
+FArgs fengine_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld);
+// X-engine launch arguments of a segment.
+XArgs xengine_args(mwax_plan p, const Segment &s);
+
+}  // namespace mwax

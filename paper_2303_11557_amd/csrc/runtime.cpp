@@ -17,13 +17,13 @@
 #include <string>
 #include <vector>
 
-#include "mwax_internal.h"
+#include "plan.h"
 
-using namespace mwax;
+namespace mwax {
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
 mwax_status fail(mwax_status s, const char *fmt, ...) {
     char buf[512];
@@ -45,85 +45,15 @@ mwax_status hip_fail(hipError_t e, const char *what) {
                 "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr int64_t kCalSamples = 131072;   // calibration window: 0.1024 s at 1.28 Msps
+}  // namespace mwax
 
-struct Segment {
-    int64_t j;        // integration index
-    int slot;         // device slot
-    int64_t frame0;   // first spectrum of the segment within the call
-    int64_t nframes;  // spectra in the segment
-    int64_t grp0;     // first row group in the channel-major buffer
-    int64_t ngrp;     // row groups
-    int64_t local0;   // offset of the first spectrum within integration j
-};
-
-}  // namespace
-
-struct mwax_plan_s {
-    mwax_config cfg{};
-    mwax_dims d{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-    int L = 0, G = 0, n_in = 0, xprec = 0, R = 1, ntiles = 0;
-    int64_t T = 0, P = 0;
-
-    uint8_t *chan = nullptr;
-    int64_t NG = 0;
-    void *integ = nullptr;
-    size_t slot_bytes = 0;
-    int nslots = 0;
-    float *scales = nullptr;        // [nslots][2][L] (s, inv_s)
-    float *fixed = nullptr;         // [2][L] user scales
-    float *ones = nullptr;          // [2][L] = 1
-    float2 *tw = nullptr;
-    double *stats = nullptr;        // [kStatsMaxWG][L]
-
-    int64_t g_chan = 0;             // stream spectra channelised (incl. the pending block)
-    bool pending = false;           // a channelised block awaits mwax_correlate
-    bool have_block = false;        // the buffer holds a block (for read-back)
-    int64_t block_spectra = 0;
-    std::vector<Segment> segs;
-    std::vector<int64_t> slot_owner, slot_count;
-    int64_t next_emit = 0;
-    bool fixed_mode = false;
-
-    bool timing = false;
-    struct Ev { hipEvent_t a, b; int fam; };
-    std::vector<Ev> events;
-    std::vector<hipEvent_t> pool;
-    double t_ms[3] = {0, 0, 0};
-    int64_t t_n[3] = {0, 0, 0};
-};
+using namespace mwax;
 
 namespace {
-
-hipEvent_t get_event(mwax_plan p) {
-    if (!p->pool.empty()) {
-        hipEvent_t e = p->pool.back();
-        p->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Wraps a launch with timing events when timing is on.
-template <class F>
-hipError_t timed(mwax_plan p, int fam, F &&launch) {
-    if (!p->timing) return launch();
-    hipEvent_t a = get_event(p), b = get_event(p);
-    if (!a || !b) return hipErrorOutOfMemory;
-    (void)hipEventRecord(a, p->stream);
-    hipError_t e = launch();
-    (void)hipEventRecord(b, p->stream);
-    p->events.push_back({a, b, fam});
-    return e;
-}
-
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+}  // namespace
 
-mwax_status derive(const mwax_config *cfg, mwax_dims *o) {
+mwax_status mwax::derive(const mwax_config *cfg, mwax_dims *o) {
     if (!cfg || !o) return fail(MWAX_E_INVAL, "null configuration or output");
     if (cfg->n_pols != 2) return fail(MWAX_E_INVAL, "n_pols must be 2 (got %d)", cfg->n_pols);
     if (cfg->n_tiles < 1 || cfg->n_tiles > 1024)
@@ -175,7 +105,7 @@ mwax_status derive(const mwax_config *cfg, mwax_dims *o) {
     return MWAX_OK;
 }
 
-void free_plan(mwax_plan p) {
+void mwax::free_plan(mwax_plan p) {
     if (!p) return;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
@@ -194,8 +124,7 @@ void free_plan(mwax_plan p) {
     delete p;
 }
 
-// Split a block of M spectra at integration boundaries and check slot use.
-mwax_status plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out) {
+mwax_status mwax::plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out) {
     out.clear();
     int64_t g = p->g_chan, done = 0, grp = 0;
     while (done < M) {
@@ -228,6 +157,58 @@ mwax_status plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out) {
     return MWAX_OK;
 }
 
+FArgs mwax::calib_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld) {
+    const int64_t ncal = std::min(p->d.cal_spectra, s.nframes);
+    FArgs a{};
+    a.volts = volts;
+    a.ld = ld;
+    a.frame0 = s.frame0;
+    a.nframes = ncal;
+    a.n_in = p->n_in;
+    a.R = p->R;
+    a.ngrp = (int32_t)((ncal + p->G - 1) / p->G);
+    a.stats_mode = 1;
+    a.tw = p->tw;
+    a.stats = p->stats;
+    return a;
+}
+
+FArgs mwax::fengine_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld) {
+    FArgs a{};
+    a.volts = volts;
+    a.ld = ld;
+    a.frame0 = s.frame0;
+    a.nframes = s.nframes;
+    a.chan = p->chan;
+    a.NG = p->NG;
+    a.grp0 = s.grp0;
+    a.n_in = p->n_in;
+    a.R = p->R;
+    a.ngrp = (int32_t)s.ngrp;
+    a.stats_mode = 0;
+    a.tw = p->tw;
+    a.inv_s = p->scales + (size_t)s.slot * 2 * p->L + p->L;
+    a.half_scale = std::ldexp(1.0f, -fp16_exponent(p->L));
+    return a;
+}
+
+XArgs mwax::xengine_args(mwax_plan p, const Segment &s) {
+    XArgs a{};
+    a.chan = p->chan;
+    a.NG = p->NG;
+    a.grp0 = s.grp0;
+    a.ngrp = (int32_t)s.ngrp;
+    a.n_in = p->n_in;
+    a.L = p->L;
+    a.ntiles = p->ntiles;
+    a.tile = xengine_tile(p->xprec);
+    a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
+    a.P = p->P;
+    return a;
+}
+
+namespace {
+
 // Set the scales of the integrations that begin in this block (INT8 plans).
 mwax_status begin_integrations(mwax_plan p, const int8_t *volts, int64_t ld, bool from_voltages) {
     for (const Segment &s : p->segs) {
@@ -240,23 +221,12 @@ mwax_status begin_integrations(mwax_plan p, const int8_t *volts, int64_t ld, boo
         if (p->fixed_mode || !from_voltages) {
             e = launch_copy_scales(p->fixed_mode ? p->fixed : p->ones, dst, 2 * p->L, p->stream);
         } else {
-            const int64_t ncal = std::min(p->d.cal_spectra, s.nframes);
-            FArgs a{};
-            a.volts = volts;
-            a.ld = ld;
-            a.frame0 = s.frame0;
-            a.nframes = ncal;
-            a.n_in = p->n_in;
-            a.R = p->R;
-            a.ngrp = (int32_t)((ncal + p->G - 1) / p->G);
-            a.stats_mode = 1;
-            a.tw = p->tw;
-            a.stats = p->stats;
-            e = timed(p, 0, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
+            const FArgs a = calib_args(p, s, volts, ld);
+            e = timed(p, 3, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
             if (e == hipSuccess) {
                 const int nwg = fengine_grid(p->n_in, p->R, a.ngrp, true);
-                e = timed(p, 0, [&] {
-                    return launch_calib_finish(p->stats, nwg, p->L, (double)ncal * p->n_in, dst, p->stream);
+                e = timed(p, 3, [&] {
+                    return launch_calib_finish(p->stats, nwg, p->L, (double)a.nframes * p->n_in, dst, p->stream);
                 });
             }
         }
@@ -355,6 +325,7 @@ mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan
 }
 
 mwax_status mwax_plan_destroy(mwax_plan p) {
+    if (p && p->in_batch) return fail(MWAX_E_INVAL, "this plan belongs to a batch: destroy the batch");
     free_plan(p);
     return ok();
 }
@@ -383,23 +354,8 @@ mwax_status mwax_channelise(mwax_plan p, const int8_t *d_volts, int64_t n_sample
     p->segs = segs;
     st = begin_integrations(p, d_volts, ld_samples, true);
     if (st != MWAX_OK) return st;
-    const float half_scale = std::ldexp(1.0f, -fp16_exponent(p->L));
     for (const Segment &s : p->segs) {
-        FArgs a{};
-        a.volts = d_volts;
-        a.ld = ld_samples;
-        a.frame0 = s.frame0;
-        a.nframes = s.nframes;
-        a.chan = p->chan;
-        a.NG = p->NG;
-        a.grp0 = s.grp0;
-        a.n_in = p->n_in;
-        a.R = p->R;
-        a.ngrp = (int32_t)s.ngrp;
-        a.stats_mode = 0;
-        a.tw = p->tw;
-        a.inv_s = p->scales + (size_t)s.slot * 2 * p->L + p->L;
-        a.half_scale = half_scale;
+        const FArgs a = fengine_args(p, s, d_volts, ld_samples);
         hipError_t e = timed(p, 0, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
         if (e != hipSuccess) return hip_fail(e, "F-engine launch");
     }
@@ -480,17 +436,7 @@ mwax_status mwax_correlate(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     if (!p->pending) return fail(MWAX_E_STATE, "no fresh channelised block to correlate");
     for (const Segment &s : p->segs) {
-        XArgs a{};
-        a.chan = p->chan;
-        a.NG = p->NG;
-        a.grp0 = s.grp0;
-        a.ngrp = (int32_t)s.ngrp;
-        a.n_in = p->n_in;
-        a.L = p->L;
-        a.ntiles = p->ntiles;
-        a.tile = xengine_tile(p->xprec);
-        a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
-        a.P = p->P;
+        const XArgs a = xengine_args(p, s);
         hipError_t e = timed(p, 1, [&] { return launch_xengine(p->xprec, a, p->stream); });
         if (e != hipSuccess) return hip_fail(e, "X-engine launch");
         p->slot_count[s.slot] += s.nframes;
@@ -615,7 +561,7 @@ mwax_status mwax_set_timing(mwax_plan p, int32_t enable) {
 
 mwax_status mwax_kernel_time(mwax_plan p, int32_t family, double *total_ms, int64_t *launches) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
-    if (family < 0 || family > 2 || !total_ms || !launches) return fail(MWAX_E_INVAL, "bad arguments");
+    if (family < 0 || family > 3 || !total_ms || !launches) return fail(MWAX_E_INVAL, "bad arguments");
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(e, "stream synchronisation");
     for (auto &ev : p->events) {

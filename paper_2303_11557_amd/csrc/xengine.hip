@@ -110,9 +110,12 @@ constexpr int kGroupPitch = 2 * kHalfPitch;
 constexpr int kPanel = kXG * kGroupPitch;   // one panel (A, B or B2) of a stage
 constexpr int kStage = 3 * kPanel;
 
-template <int XP, bool ACTIVE>
+// ATOMIC: flush with int64 atomic adds (another workgroup may be flushing other
+// row groups of the same tile at the same time).
+template <int XP, bool ACTIVE, bool ATOMIC = false>
 __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, int c, int rowA0, int rowB0,
                                                   int wr, int wc) {
+    static_assert(!ATOMIC || XP == MWAX_X_INT8, "atomic flushes are exact for integer partials only");
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -247,7 +250,12 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
                         const int n1 = fr0 + RB * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
                         if (n1 < a.n_in && n2 <= n1) {
                             const int64_t p = (int64_t)n1 * (n1 + 1) / 2 + n2;
-                            if constexpr (XP == MWAX_X_INT8) {
+                            if constexpr (ATOMIC) {
+                                unsigned long long *dst =
+                                    reinterpret_cast<unsigned long long *>(ibase) + 2 * ((int64_t)c * a.P + p);
+                                atomicAdd(dst, (unsigned long long)(long long)re[mb][nb2][r]);
+                                atomicAdd(dst + 1, (unsigned long long)(long long)im[mb][nb2][r]);
+                            } else if constexpr (XP == MWAX_X_INT8) {
                                 longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
                                 longlong2 v = *dst;
                                 v.x += re[mb][nb2][r];
@@ -283,6 +291,60 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
     const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
     if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
     else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
+}
+
+// Persistent batched form (see XBatchArgs): each workgroup takes items from the
+// queue of its XCD until it is empty, then from the other queues in turn, and
+// exits when all are empty.  Every item is one tile of one channel over one chunk
+// of row groups, run by the same loop as the single-plan kernel.
+template <int XP>
+__global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
+    __shared__ __align__(16) uint8_t lds[2 * kStage];
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+    const int home = blockIdx.x & (kXQueues - 1);
+    for (int v = 0; v < kXQueues; ++v) {
+        const int q = (home + v) & (kXQueues - 1);
+        const int q0 = b.qbeg[q], qn = b.qbeg[q + 1] - q0;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[q * kXCounterStride], 1);
+            __syncthreads();
+            const int k = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (k >= qn) break;
+            const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)b.items[q0 + k]);
+            const int d = (int)(it >> 24), c = (int)((it >> 14) & 1023), t = (int)((it >> 6) & 255);
+            const int ks = (int)(it & 63);
+            const XDesc xd = b.desc[d];
+            XArgs a{};
+            a.chan = xd.chan;
+            a.NG = xd.NG;
+            a.grp0 = xd.grp0 + (int64_t)ks * xd.kchunk;
+            a.ngrp = min(xd.kchunk, xd.ngrp - ks * xd.kchunk);
+            a.n_in = xd.n_in;
+            a.integ = xd.integ;
+            a.P = xd.P;
+            int I, J;
+            tile_ij(t, I, J);
+            const int rowA0 = I * kTile, rowB0 = J * kTile;
+            const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
+            if constexpr (XP == MWAX_X_INT8) {
+                if (xd.ksplit > 1) {
+                    if (idle) xengine_tile_loop<XP, false, true>(a, lds, c, rowA0, rowB0, wr, wc);
+                    else xengine_tile_loop<XP, true, true>(a, lds, c, rowA0, rowB0, wr, wc);
+                    continue;
+                }
+            }
+            if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
+        }
+    }
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -426,6 +488,38 @@ hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s) {
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_xengine_batch(int xprec, const XBatchArgs &b, int grid, hipStream_t s) {
+    if (grid < 1) return hipSuccess;
+    switch (xprec) {
+        case MWAX_X_INT8:
+            hipLaunchKernelGGL(xengine_batch<MWAX_X_INT8>, dim3((unsigned)grid), dim3(kThreads), 0, s, b);
+            break;
+        case MWAX_X_FP16:
+            hipLaunchKernelGGL(xengine_batch<MWAX_X_FP16>, dim3((unsigned)grid), dim3(kThreads), 0, s, b);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+int xengine_batch_max_grid(int xprec, int device) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        cus = 256;
+    const void *fn = xprec == MWAX_X_INT8 ? reinterpret_cast<const void *>(&xengine_batch<MWAX_X_INT8>)
+                                          : reinterpret_cast<const void *>(&xengine_batch<MWAX_X_FP16>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
 }
 
 }  // namespace mwax

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmwax.so")
 MWAX_OK, MWAX_E_INVAL, MWAX_E_NOMEM, MWAX_E_DEVICE, MWAX_E_STATE, MWAX_E_UNSUPPORTED = range(6)
 X_FP32, X_FP16, X_INT8 = 0, 1, 2
 ORDER_CHAN_TRI, ORDER_TILE_BL = 0, 1
-FAMILY_F, FAMILY_X, FAMILY_PACK = 0, 1, 2
+FAMILY_F, FAMILY_X, FAMILY_PACK, FAMILY_CALIB, FAMILY_STEP = 0, 1, 2, 3, 4
 F_S = 1.28e6
 
 _PREC = {"fp32": X_FP32, "fp16": X_FP16, "int8": X_INT8}
@@ -26,6 +26,9 @@ EXPORTS = (
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
+    "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
+    "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
+    "mwax_batch_set_timing", "mwax_batch_kernel_time", "mwax_batch_sync",
 )
 
 
@@ -88,6 +91,17 @@ def lib():
             "mwax_sync": [vp],
             "mwax_set_timing": [vp, i32],
             "mwax_kernel_time": [vp, i32, P(ctypes.c_double), P(i64)],
+            "mwax_batch_create": [P(Config), i32, vp, P(vp)],
+            "mwax_batch_destroy": [vp],
+            "mwax_batch_plan": [vp, i32, P(vp)],
+            "mwax_batch_run": [vp, P(vp), P(i64), P(i64)],
+            "mwax_batch_autotune": [vp, P(vp), P(i64), P(i64), i32],
+            "mwax_batch_get_tuning": [vp, P(i32), P(i32)],
+            "mwax_batch_set_tuning": [vp, P(i32), i32],
+            "mwax_batch_set_graph": [vp, i32],
+            "mwax_batch_set_timing": [vp, i32],
+            "mwax_batch_kernel_time": [vp, i32, P(ctypes.c_double), P(i64)],
+            "mwax_batch_sync": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -126,18 +140,26 @@ def derive(cfg: Config) -> Dims:
 
 
 class Plan:
-    """One correlator plan on the current device and torch's current stream."""
+    """One correlator plan on the current device and torch's current stream.
 
-    def __init__(self, cfg: Config, stream=None):
+    A plan that belongs to a batch (``Batch.plans``) wraps the batch's handle and
+    is released with the batch."""
+
+    def __init__(self, cfg: Config, stream=None, _handle=None):
         import torch
         self.torch = torch
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        self.stream = stream
         self.cfg = cfg
-        h = ctypes.c_void_p()
-        _check(lib().mwax_plan_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
-                                      ctypes.byref(h)))
+        self._owned = _handle is None
+        if _handle is None:
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            self.stream = stream
+            h = ctypes.c_void_p()
+            _check(lib().mwax_plan_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(h)))
+        else:
+            self.stream = None
+            h = _handle
         self.h = h
         d = Dims()
         _check(lib().mwax_plan_get_dims(self.h, ctypes.byref(d)))
@@ -151,7 +173,8 @@ class Plan:
     # -- lifetime -----------------------------------------------------------
     def close(self):
         if getattr(self, "h", None) and self.h.value:
-            lib().mwax_plan_destroy(self.h)
+            if self._owned:
+                lib().mwax_plan_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):
@@ -248,6 +271,101 @@ class Plan:
         n = ctypes.c_int64()
         _check(lib().mwax_kernel_time(self.h, family, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Many plans run as one unit of device work per call (see mwax.h, Batches).
+
+    stream=None lets the library create the batch's stream, which synchronises
+    with the legacy default stream torch uses unless told otherwise."""
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+        self.torch = torch
+        self.cfgs = list(cfgs)
+        self.n = len(self.cfgs)
+        arr = (Config * self.n)(*self.cfgs)
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p()
+        _check(lib().mwax_batch_create(arr, self.n, sp, ctypes.byref(h)))
+        self.h = h
+        self.plans = []
+        for i, c in enumerate(self.cfgs):
+            ph = ctypes.c_void_p()
+            _check(lib().mwax_batch_plan(self.h, i, ctypes.byref(ph)))
+            self.plans.append(Plan(c, _handle=ph))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            for p in self.plans:
+                p.close()
+            lib().mwax_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _arrays(self, volts, n_samples):
+        ptrs = (ctypes.c_void_p * self.n)()
+        ns = (ctypes.c_int64 * self.n)()
+        ld = (ctypes.c_int64 * self.n)()
+        t = self.torch
+        for i, v in enumerate(volts):
+            if v is None:
+                continue
+            p = self.plans[i]
+            assert v.dtype == t.int8 and v.is_cuda and v.dim() == 3
+            assert v.shape[0] == p.n_in and v.shape[2] == 2 and v.stride(2) == 1 and v.stride(1) == 2
+            ptrs[i] = v.data_ptr()
+            ns[i] = v.shape[1] if n_samples is None or n_samples[i] is None else int(n_samples[i])
+            ld[i] = v.stride(0) // 2
+        return ptrs, ns, ld
+
+    def run(self, volts, n_samples=None):
+        """volts: one int8 [n_inputs][>= n][2] tensor (or None: skip) per instance."""
+        assert len(volts) == self.n
+        ptrs, ns, ld = self._arrays(volts, n_samples)
+        _check(lib().mwax_batch_run(self.h, ptrs, ns, ld))
+
+    def autotune(self, volts, trials=3):
+        assert len(volts) == self.n
+        ptrs, ns, ld = self._arrays(volts, None)
+        _check(lib().mwax_batch_autotune(self.h, ptrs, ns, ld, int(trials)))
+        return self.tuning()
+
+    def tuning(self):
+        kc = (ctypes.c_int32 * self.n)()
+        g = ctypes.c_int32()
+        _check(lib().mwax_batch_get_tuning(self.h, kc, ctypes.byref(g)))
+        return list(kc), g.value
+
+    def set_tuning(self, kchunk=None, grid=0):
+        kc = None if kchunk is None else (ctypes.c_int32 * self.n)(*[int(k) for k in kchunk])
+        _check(lib().mwax_batch_set_tuning(self.h, kc, int(grid)))
+
+    def set_graph(self, on=True):
+        _check(lib().mwax_batch_set_graph(self.h, int(bool(on))))
+
+    def set_timing(self, on=True):
+        _check(lib().mwax_batch_set_timing(self.h, int(bool(on))))
+
+    def kernel_time(self, family):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().mwax_batch_kernel_time(self.h, family, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def sync(self):
+        _check(lib().mwax_batch_sync(self.h))
 
 
 def pair_index(n1, n2):

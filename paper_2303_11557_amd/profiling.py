@@ -1,0 +1,147 @@
+"""Summaries of rocprofv3 CSV output for the hot-path kernels.
+
+    python -m paper_2303_11557_amd.profiling stats <kernel_stats.csv>
+        per-kernel dispatch count and average / min / max duration (markdown)
+
+    python -m paper_2303_11557_amd.profiling traffic <fetch.csv> <write.csv> [--out traffic.json]
+        HBM bytes per dispatch of each hot-path kernel from FETCH_SIZE and
+        WRITE_SIZE counter runs.  Both counters are scaled by what they read for
+        the largest device-to-device copy in the same run (a copy of known size:
+        bytes read = bytes written = its buffer size), so that the figures are
+        bytes, whatever unit and sampling the counters use.
+
+The traffic file records, per kernel, the SHA-256 prefix of the kernel's source
+file, so that a reader can tell whether the figures still describe the code.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = {
+    "fengine": os.path.join(HERE, "csrc", "fengine.hip"),
+    "xengine": os.path.join(HERE, "csrc", "xengine.hip"),
+    "pack": os.path.join(HERE, "csrc", "pack.hip"),
+}
+PREC = {"0": "fp32", "1": "fp16", "2": "int8"}
+
+
+def source_sha(family):
+    with open(SOURCES[family], "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name):
+    """Kernel name without namespaces and argument lists, template arguments kept."""
+    n = name.replace("mwax::(anonymous namespace)::", "").replace("mwax::", "")
+    n = re.sub(r"^void ", "", n)
+    depth, out = 0, []
+    for ch in n:           # drop the parenthesised argument list (outside templates)
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def kernel_key(name):
+    """Stable key of a hot-path kernel ('fengine_int8', 'xengine_int8', ...), or None."""
+    s = short_name(name)
+    m = re.match(r"fengine_kernel<(\d+), (\d), (false|true)>", s)
+    if m:
+        return f"fengine_{PREC[m.group(2)]}" + ("_stats" if m.group(3) == "true" else "")
+    m = re.match(r"xengine_mfma<(\d)>", s)
+    if m:
+        return f"xengine_{PREC[m.group(1)]}"
+    if s.startswith("xengine_f32"):
+        return "xengine_fp32"
+    if s.startswith("pack_"):
+        return s.split("<")[0]
+    return None
+
+
+def stats_table(path):
+    rows = list(csv.DictReader(open(path)))
+    lines = ["| kernel | dispatches | avg ms | min ms | max ms | total ms |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| {} | {} | {:.4f} | {:.4f} | {:.4f} | {:.3f} |".format(
+            short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6,
+            float(r["MaxNs"]) / 1e6, float(r["TotalDurationNs"]) / 1e6))
+    return "\n".join(lines)
+
+
+def counter_per_dispatch(path, counter):
+    vals = collections.OrderedDict()
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+        vals[k] = vals.get(k, 0.0) + float(r["Counter_Value"])
+    return vals
+
+
+def traffic(fetch_csv, write_csv, copy_bytes):
+    fetch = counter_per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = counter_per_dispatch(write_csv, "WRITE_SIZE")
+
+    def copy_factor(vals):
+        copies = [v for (d, n), v in vals.items() if "copyBuffer" in n]
+        if not copies:
+            raise SystemExit("no device-to-device copy in the counter run (bench.py --copy-probe)")
+        return copy_bytes / max(copies)
+
+    ff, wf = copy_factor(fetch), copy_factor(write)
+    per = collections.defaultdict(lambda: {"fetch": [], "write": []})
+    for (d, n), v in fetch.items():
+        k = kernel_key(n)
+        if k:
+            per[k]["fetch"].append(v * ff)
+    for (d, n), v in write.items():
+        k = kernel_key(n)
+        if k:
+            per[k]["write"].append(v * wf)
+    out = {"copy_probe_bytes": copy_bytes, "fetch_factor_bytes_per_unit": ff,
+           "write_factor_bytes_per_unit": wf}
+    for k, v in per.items():
+        fam = k.split("_")[0]
+        fb = sum(v["fetch"]) / max(len(v["fetch"]), 1)
+        wb = sum(v["write"]) / max(len(v["write"]), 1)
+        out[k] = {"source_sha": source_sha(fam) if fam in SOURCES else None,
+                  "dispatches": len(v["fetch"]), "fetch_bytes_per_launch": fb,
+                  "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--copy-bytes", type=float, default=float(4 << 30))
+    t.add_argument("--out")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(stats_table(a.csv))
+    else:
+        tr = traffic(a.fetch_csv, a.write_csv, a.copy_bytes)
+        txt = json.dumps(tr, indent=1, sort_keys=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(txt + "\n")
+        print(txt)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
