@@ -89,9 +89,12 @@ def cpu_baseline(volts, L, seconds, what):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
                     help="c3: one coarse channel, 256 tiles, 8 s (the headline metric); "
-                         "c4: 24 uneven instances as one batch")
+                         "c4: 24 uneven instances as one batch; c5: 24 channels streamed in 8 s blocks")
+    ap.add_argument("--c5-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
+    ap.add_argument("--c5-paced-rounds", type=int, default=4, help="8 s blocks per channel, real-time paced")
+    ap.add_argument("--c5-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--xprec", default="int8", choices=["int8", "fp16", "fp32"])
@@ -204,6 +207,104 @@ def main_c4(args):
     print(json.dumps(line), flush=True)
 
 
+def main_c5(args):
+    """Streaming: 24 coarse channels x 256 tiles, continuous 8 s blocks, 2 s
+    integrations on the device, int8 X-engine, admission by HBM budget.
+    (i) blocks resident in the pool (made once by the device generator): the
+    compute real-time factor; (ii) every block copied from a pinned host buffer
+    (replayed at shifting offsets): end to end over the host link; a paced run
+    of (ii) releases each round of 24 blocks every 8 s and gives the latency
+    from a block's arrival (its last sample) to its visibilities on the device."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+    from paper_2303_11557_amd.mwax import Stream, device_view, make_config
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    n_ch, n_tiles, Lc, tau = 24, 256, 128, 2.0
+    block = int(SECONDS * F_S)
+    call = int(F_S)
+    cfg = make_config(n_tiles, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=call)
+    d = mwax.derive(cfg)
+    n_in, P = d.n_inputs, d.n_pairs
+    budget = int(args.c5_budget_gb * 1e9)
+    pad = 1 << 16
+    out = {}
+    with Stream(cfg, n_ch, block, budget, out_depth=6) as s:
+        slots = s.info.pool_slots
+        # (i) pre-fill every pool buffer once with distinct generated blocks
+        for k in range(slots):
+            slot, ptr = s.acquire(0)
+            v = device_view(ptr, (n_in, block, 2), torch.int8)
+            synth.device_volts(v, seed=synth.MWAX_SEED + 4, L=Lc, s0=k * block,
+                               sources=[synth.Source(2.0, 17)], stream=s.info.ingest_stream)
+        torch.cuda.synchronize()
+        free = list(range(slots))            # acquired, holding data
+
+        def run(rounds, variant, paced, host=None):
+            recs = []
+            t_start = s.now()
+            nonlocal free
+            for r in range(rounds):
+                t_arr = t_start + SECONDS * (r + 1) if paced else None
+                if paced:
+                    while s.now() < t_arr:
+                        recs.extend(s.poll(0))
+                        time.sleep(0.002)
+                for ch in range(n_ch):
+                    slot = free.pop() if free else s.acquire(-1)[0]
+                    if variant == "ii":
+                        off = ((r * n_ch + ch) * 4096) % pad
+                        s.copy_in(slot, host[:, off:off + block])
+                    s.submit(slot, ch, t_arr if paced else s.now())
+                    recs.extend(s.poll(0))
+            while len(recs) < rounds * n_ch:
+                recs.extend(s.poll(-1))
+            wall = max(r["t_ready_s"] for r in recs) - t_start
+            lat = np.array([r["t_ready_s"] - r["t_arrival_s"] for r in recs])
+            data_s = rounds * SECONDS
+            return {"blocks": len(recs), "wall_s": round(wall, 3), "rtf": round(data_s / wall, 3),
+                    "cmac_per_s": n_ch * rounds * P * block / wall,
+                    "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                    "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+                    "latency_max_s": round(float(lat.max()), 4),
+                    "integrations": int(sum(r["n_ints"] for r in recs))}
+
+        out["warmup"] = run(1, "i", False)
+        out["device_resident"] = run(args.c5_rounds, "i", False)
+        # (ii) pinned host pool: one block plus a margin, filled from the device generator
+        host = torch.empty((n_in, block + pad, 2), dtype=torch.int8, pin_memory=True)
+        gen = torch.empty((n_in, block + pad, 2), dtype=torch.int8, device="cuda")
+        synth.device_volts(gen, seed=synth.MWAX_SEED + 4 + 1, L=Lc, sources=[synth.Source(2.0, 17)])
+        host.copy_(gen)
+        del gen
+        torch.cuda.empty_cache()
+        out["host_link"] = run(max(1, args.c5_paced_rounds), "ii", False, host)
+        out["paced_host_link"] = run(args.c5_paced_rounds, "ii", True, host)
+        info = s.info
+
+    dr = out["device_resident"]
+    line = {
+        "metric": "real-time factor & block latency, 24 coarse channels x 256 tiles streamed in 8 s blocks",
+        "value": dr["cmac_per_s"], "unit": "CMAC/s", "n_gpus": 1, "steps": args.c5_rounds, "warmup": 1,
+        "ms_per_step": round(dr["wall_s"] * 1e3 / args.c5_rounds, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.xprec, "data": "synthetic",
+        "config": {"workload": "24 channels x 256 tiles x 2 pols, continuous 8 s blocks of complex int8 "
+                               "sigma=8 voltages + 1 source, 128-pt FFT, 2 s integrations on device, "
+                               "1 s plan calls, admission by HBM budget",
+                   "channels": n_ch, "block_samples": block, "pool_slots": info.pool_slots,
+                   "hbm_budget_bytes": budget, "device_bytes": info.device_bytes},
+        "rtf": dr["rtf"],
+        "latency_p50_s": out["paced_host_link"]["latency_p50_s"],
+        "latency_p99_s": out["paced_host_link"]["latency_p99_s"],
+        "runs": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -213,6 +314,8 @@ def main():
 
     if args.workload == "c4":
         return main_c4(args)
+    if args.workload == "c5":
+        return main_c5(args)
 
     import torch
 

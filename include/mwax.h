@@ -288,6 +288,89 @@ mwax_status mwax_batch_kernel_time(mwax_batch b, int32_t family, double *total_m
 /* Wait for the batch's stream. */
 mwax_status mwax_batch_sync(mwax_batch b);
 
+/* ------------------------------------------------------------------------
+ * Real-time streaming.  Voltages reach a server as 8 s sub-observation blocks
+ * per coarse channel (Sec. 2.4), which must be correlated as fast as they
+ * arrive (Sec. 3.4: under 8 s per 8 s block).  A stream keeps one plan per
+ * coarse channel (integrators stay on the device across blocks) and a pool of
+ * device block buffers whose number is set by an HBM budget: admission
+ * (mwax_stream_acquire) hands out a free buffer, or waits, or refuses when the
+ * budget is exhausted.  Blocks are written into their buffer on the stream's
+ * ingest stream (a copy from pinned host memory, mwax_stream_copy_in, or any
+ * producer kernel), then submitted; the compute stream waits for the ingest,
+ * runs the channel's plan over the block in calls of cfg.max_samples samples,
+ * and emits every completed integration into the channel's device output ring.
+ * Block latency = ready time - arrival time, with the ready time taken from a
+ * HIP event timestamp on the stream clock.
+ * ------------------------------------------------------------------------ */
+typedef struct mwax_stream_s *mwax_stream;
+
+typedef struct {
+    int32_t n_channels;         /* coarse channels, 1..64; channel k runs plan k         */
+    int32_t out_depth;          /* integrations each channel's output ring holds (>= 1)   */
+    mwax_config cfg;            /* every channel's plan; max_samples = samples per call    */
+    int64_t block_samples;      /* samples per input per block; a multiple of
+                                   cfg.max_samples                                         */
+    uint64_t hbm_budget_bytes;  /* device bytes for resident voltage blocks; the pool holds
+                                   budget / block_bytes buffers (at least 1 must fit)      */
+} mwax_stream_config;
+
+typedef struct {
+    int32_t pool_slots;         /* block buffers (admission capacity)                      */
+    int32_t n_inputs;
+    uint64_t block_bytes;       /* n_inputs * block_samples * 2                            */
+    int64_t block_ld;           /* samples between input rows of a buffer (block_samples)  */
+    void *ingest_stream;        /* hipStream_t to write buffers on before submitting       */
+    void *compute_stream;       /* hipStream_t the plans run on                            */
+    uint64_t device_bytes;      /* device memory held: pool, plans, output rings           */
+} mwax_stream_info;
+
+typedef struct {
+    int32_t channel;
+    int32_t slot;
+    int64_t block;              /* the channel's block sequence number                      */
+    int64_t first_int;          /* first integration index emitted by this block            */
+    int32_t n_ints;             /* integrations completed and emitted by this block         */
+    int32_t reserved;
+    double t_arrival_s;         /* as given to mwax_stream_submit (stream clock)            */
+    double t_submit_s;          /* when mwax_stream_submit was called                        */
+    double t_ready_s;           /* when its visibilities were in the output ring             */
+} mwax_block_done;
+
+/* Create a stream on the current device with its own ingest and compute
+ * streams (default priority).  Errors: MWAX_E_INVAL (configuration, or a
+ * budget that holds no block), MWAX_E_NOMEM, MWAX_E_DEVICE. */
+mwax_status mwax_stream_create(const mwax_stream_config *cfg, mwax_stream *out);
+/* Wait for all work, release everything. */
+mwax_status mwax_stream_destroy(mwax_stream s);
+mwax_status mwax_stream_get_info(mwax_stream s, mwax_stream_info *out);
+/* Channel k's plan (owned by the stream). */
+mwax_status mwax_stream_plan(mwax_stream s, int32_t channel, mwax_plan *out);
+/* Seconds on the stream clock (steady host clock, zero at creation). */
+mwax_status mwax_stream_now(mwax_stream s, double *t);
+
+/* Admission: a free pool buffer (device int8 [n_inputs][block_ld][2]).  Waits
+ * up to wait_ms milliseconds (0: do not wait; < 0: wait until one frees) for a
+ * submitted block to finish; MWAX_E_STATE if the budget stays exhausted.  The
+ * buffer keeps its previous contents until written. */
+mwax_status mwax_stream_acquire(mwax_stream s, int32_t wait_ms, int32_t *slot, int8_t **d_block);
+/* Enqueue on the ingest stream a copy of one block from host memory h_block
+ * ([n_inputs][h_ld][2], h_ld >= block_samples; pinned for an asynchronous
+ * copy) into an acquired buffer.  The host memory must stay valid until the
+ * block is reported done. */
+mwax_status mwax_stream_copy_in(mwax_stream s, int32_t slot, const int8_t *h_block, int64_t h_ld);
+/* Submit an acquired buffer as channel's next block (arrival time t_arrival_s
+ * on the stream clock).  Enqueues the channel's work after everything enqueued
+ * so far on the ingest stream.  MWAX_E_STATE if the slot is not acquired. */
+mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, double t_arrival_s);
+/* Report finished blocks in submission order (their buffers return to the
+ * pool): up to max records into out, count in *n.  wait_ms as in acquire, for
+ * at least one record when blocks are in flight. */
+mwax_status mwax_stream_poll(mwax_stream s, int32_t wait_ms, mwax_block_done *out, int32_t max, int32_t *n);
+/* Device pointer of channel's integration j ([L][P] complex64, CHAN_TRI) while
+ * it is still in the ring (the out_depth most recent); MWAX_E_STATE if not. */
+mwax_status mwax_stream_vis(mwax_stream s, int32_t channel, int64_t j, void **d_vis);
+
 /* Message for the last error of the calling thread (empty if none). */
 const char *mwax_last_error(void);
 

@@ -55,7 +55,7 @@ struct mwax_plan_s {
     std::vector<int64_t> slot_owner, slot_count;
     int64_t next_emit = 0;
     bool fixed_mode = false;
-    bool in_batch = false;          // owned by a batch (destroyed with it)
+    bool in_batch = false;          // owned by a batch or stream (destroyed with it)
 
     bool timing = false;
     struct Ev { hipEvent_t a, b; int fam; };

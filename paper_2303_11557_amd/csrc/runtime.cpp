@@ -325,7 +325,7 @@ mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan
 }
 
 mwax_status mwax_plan_destroy(mwax_plan p) {
-    if (p && p->in_batch) return fail(MWAX_E_INVAL, "this plan belongs to a batch: destroy the batch");
+    if (p && p->in_batch) return fail(MWAX_E_INVAL, "this plan belongs to a batch or stream: destroy that instead");
     free_plan(p);
     return ok();
 }

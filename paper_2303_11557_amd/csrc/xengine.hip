@@ -21,6 +21,8 @@
 //   FP32: vector ALUs, 4 x 8 complex outputs per thread, two-level FP32
 //         partials (see xengine_f32) flushed to FP64 integrators every 2048
 //         spectra.
+#include <type_traits>
+
 #include "mwax_internal.h"
 
 namespace mwax {
@@ -105,6 +107,7 @@ struct MfmaT<MWAX_X_FP16> {
 // Accumulators are flushed into the integrators after each chunk of at most
 // kFlushGroups groups.
 constexpr int kXG = 2;                      // row groups per stage
+constexpr int kPF = 1;                      // stages of global loads in flight (1 or 2)
 constexpr int kHalfPitch = kTile * 16 + 64; // LDS bytes per half of a group (padded)
 constexpr int kGroupPitch = 2 * kHalfPitch;
 constexpr int kPanel = kXG * kGroupPitch;   // one panel (A, B or B2) of a stage
@@ -136,30 +139,34 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
     const int lds_off = sh * kHalfPitch + srow * 16;
     const int lds_off2 = (1 - sh) * kHalfPitch + srow * 16;
 
-    uint4 ra[kXG], rb[kXG];
-    auto load_stage = [&](int s) {
+    // kPF register sets of staged loads: stage k is loaded into set k % kPF at
+    // iteration k - 1 - kPF and written to LDS at iteration k - 1.
+    uint4 ra[kPF][kXG], rb[kPF][kXG];
+    auto load_stage = [&](int s, auto set_c) {
+        constexpr int set = decltype(set_c)::value;
 #pragma unroll
         for (int k = 0; k < kXG; ++k) {
             const int g = s * kXG + k;
             if (g < a.ngrp) {
                 const int64_t off = (int64_t)g * gstride;
-                ra[k] = *reinterpret_cast<const uint4 *>(pA + off);
-                rb[k] = *reinterpret_cast<const uint4 *>(pB + off);
+                ra[set][k] = *reinterpret_cast<const uint4 *>(pA + off);
+                rb[set][k] = *reinterpret_cast<const uint4 *>(pB + off);
             } else {
-                ra[k] = make_uint4(0u, 0u, 0u, 0u);
-                rb[k] = make_uint4(0u, 0u, 0u, 0u);
+                ra[set][k] = make_uint4(0u, 0u, 0u, 0u);
+                rb[set][k] = make_uint4(0u, 0u, 0u, 0u);
             }
         }
     };
-    auto store_stage = [&](int buf) {
+    auto store_stage = [&](int buf, auto set_c) {
+        constexpr int set = decltype(set_c)::value;
         uint8_t *st = lds + buf * kStage;
 #pragma unroll
         for (int k = 0; k < kXG; ++k) {
             const int ko = k * kGroupPitch;
-            *reinterpret_cast<uint4 *>(st + ko + lds_off) = ra[k];
-            *reinterpret_cast<uint4 *>(st + kPanel + ko + lds_off) = rb[k];
+            *reinterpret_cast<uint4 *>(st + ko + lds_off) = ra[set][k];
+            *reinterpret_cast<uint4 *>(st + kPanel + ko + lds_off) = rb[set][k];
             // B2 = [-im | re]: the re half goes to half 1, the negated im half to half 0
-            *reinterpret_cast<uint4 *>(st + 2 * kPanel + ko + lds_off2) = sh ? negate16<XP>(rb[k]) : rb[k];
+            *reinterpret_cast<uint4 *>(st + 2 * kPanel + ko + lds_off2) = sh ? negate16<XP>(rb[set][k]) : rb[set][k];
         }
     };
 
@@ -207,10 +214,27 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
     };
 
-    load_stage(0);
-    store_stage(0);
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, (kPF > 1 ? 1 : 0)>;
+    load_stage(0, S0{});
+    store_stage(0, S0{});
     __syncthreads();
-    if (nstages > 1) load_stage(1);
+    if (nstages > 1) load_stage(1, S1{});
+    if constexpr (kPF > 1) {
+        if (nstages > 2) load_stage(2, S0{});
+    }
+
+    // one iteration: matrix work on stage s, LDS store of stage s+1 from its
+    // register set, loads of stage s+1+kPF into the set just freed
+    auto iteration = [&](int s, auto set_c) {
+        if constexpr (ACTIVE) compute(s & 1);
+        if (s + 1 < nstages) {
+            store_stage((s + 1) & 1, set_c);
+            if (s + 1 + kPF < nstages) load_stage(s + 1 + kPF, set_c);
+        }
+        __syncthreads();
+    };
+    static_assert((T::kFlushGroups / kXG) % 2 == 0, "flush chunks must hold an even number of stages");
 
     for (int s0 = 0; s0 < nstages; s0 += T::kFlushGroups / kXG) {
         const int s1 = min(nstages, s0 + T::kFlushGroups / kXG);
@@ -223,15 +247,13 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
                     im[mb][nb2] = acc_t{};
                 }
         }
-        for (int s = s0; s < s1; ++s) {
-            // stage s+1 is in registers (its loads were issued during stage s-1)
-            if constexpr (ACTIVE) compute(s & 1);
-            if (s + 1 < nstages) {
-                store_stage((s + 1) & 1);
-                if (s + 2 < nstages) load_stage(s + 2);
-            }
-            __syncthreads();
+        // s0 is even: stage s+1 of an even s sits in set S1, of an odd s in set S0
+        int s = s0;
+        for (; s + 1 < s1; s += 2) {
+            iteration(s, S1{});
+            iteration(s + 1, S0{});
         }
+        if (s < s1) iteration(s, S1{});
         if constexpr (ACTIVE) {
             // flush this chunk's partial sums into the integrators.  The base is made
             // opaque here so the compiler cannot hoist 64 integrator addresses out of

@@ -29,6 +29,9 @@ EXPORTS = (
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
     "mwax_batch_set_timing", "mwax_batch_kernel_time", "mwax_batch_sync",
+    "mwax_stream_create", "mwax_stream_destroy", "mwax_stream_get_info", "mwax_stream_plan",
+    "mwax_stream_now", "mwax_stream_acquire", "mwax_stream_copy_in", "mwax_stream_submit",
+    "mwax_stream_poll", "mwax_stream_vis",
 )
 
 
@@ -54,6 +57,32 @@ class Dims(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StreamConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_channels", ctypes.c_int32), ("out_depth", ctypes.c_int32), ("cfg", Config),
+        ("block_samples", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_uint64),
+    ]
+
+
+class StreamInfo(ctypes.Structure):
+    _fields_ = [
+        ("pool_slots", ctypes.c_int32), ("n_inputs", ctypes.c_int32), ("block_bytes", ctypes.c_uint64),
+        ("block_ld", ctypes.c_int64), ("ingest_stream", ctypes.c_void_p), ("compute_stream", ctypes.c_void_p),
+        ("device_bytes", ctypes.c_uint64),
+    ]
+
+
+class BlockDone(ctypes.Structure):
+    _fields_ = [
+        ("channel", ctypes.c_int32), ("slot", ctypes.c_int32), ("block", ctypes.c_int64),
+        ("first_int", ctypes.c_int64), ("n_ints", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("t_arrival_s", ctypes.c_double), ("t_submit_s", ctypes.c_double), ("t_ready_s", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class MwaxError(RuntimeError):
@@ -102,6 +131,16 @@ def lib():
             "mwax_batch_set_timing": [vp, i32],
             "mwax_batch_kernel_time": [vp, i32, P(ctypes.c_double), P(i64)],
             "mwax_batch_sync": [vp],
+            "mwax_stream_create": [P(StreamConfig), P(vp)],
+            "mwax_stream_destroy": [vp],
+            "mwax_stream_get_info": [vp, P(StreamInfo)],
+            "mwax_stream_plan": [vp, i32, P(vp)],
+            "mwax_stream_now": [vp, P(ctypes.c_double)],
+            "mwax_stream_acquire": [vp, i32, P(i32), P(vp)],
+            "mwax_stream_copy_in": [vp, i32, vp, i64],
+            "mwax_stream_submit": [vp, i32, i32, ctypes.c_double],
+            "mwax_stream_poll": [vp, i32, P(BlockDone), i32, P(i32)],
+            "mwax_stream_vis": [vp, i32, i64, P(vp)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -366,6 +405,106 @@ class Batch:
 
     def sync(self):
         _check(lib().mwax_batch_sync(self.h))
+
+
+class Stream:
+    """Real-time streaming of voltage blocks through one plan per coarse channel
+    (see mwax.h, Real-time streaming).  The stream runs on its own HIP streams:
+    call :meth:`ingest_stream` work before :meth:`submit`, and read output-ring
+    visibilities only after :meth:`poll` has reported their block."""
+
+    def __init__(self, cfg: Config, n_channels, block_samples, hbm_budget_bytes, out_depth=8):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        sc = StreamConfig(int(n_channels), int(out_depth), cfg, int(block_samples), int(hbm_budget_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().mwax_stream_create(ctypes.byref(sc), ctypes.byref(h)))
+        self.h = h
+        info = StreamInfo()
+        _check(lib().mwax_stream_get_info(self.h, ctypes.byref(info)))
+        self.info = info
+        self.n_channels = int(n_channels)
+        self.block_samples = int(block_samples)
+        self.plans = []
+        for k in range(self.n_channels):
+            ph = ctypes.c_void_p()
+            _check(lib().mwax_stream_plan(self.h, k, ctypes.byref(ph)))
+            self.plans.append(Plan(cfg, _handle=ph))
+        self.ingest = torch.cuda.ExternalStream(info.ingest_stream)
+        self.compute = torch.cuda.ExternalStream(info.compute_stream)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            for p in self.plans:
+                p.close()
+            lib().mwax_stream_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def now(self):
+        t = ctypes.c_double()
+        _check(lib().mwax_stream_now(self.h, ctypes.byref(t)))
+        return t.value
+
+    def acquire(self, wait_ms=-1):
+        """Admission -> (slot, device pointer of the free buffer [n_inputs][block_samples][2] int8);
+        :func:`device_view` gives a tensor over it."""
+        slot = ctypes.c_int32()
+        ptr = ctypes.c_void_p()
+        _check(lib().mwax_stream_acquire(self.h, int(wait_ms), ctypes.byref(slot), ctypes.byref(ptr)))
+        return slot.value, ptr.value
+
+    def copy_in(self, slot, host_block):
+        """host_block: pinned int8 CPU tensor [n_inputs][>= block_samples][2]."""
+        assert host_block.dtype == self.torch.int8 and host_block.dim() == 3
+        assert host_block.stride(2) == 1 and host_block.stride(1) == 2
+        _check(lib().mwax_stream_copy_in(self.h, int(slot), ctypes.c_void_p(host_block.data_ptr()),
+                                         host_block.stride(0) // 2))
+
+    def submit(self, slot, channel, t_arrival):
+        _check(lib().mwax_stream_submit(self.h, int(slot), int(channel), float(t_arrival)))
+
+    def poll(self, wait_ms=0, max_records=1024):
+        recs = (BlockDone * max_records)()
+        n = ctypes.c_int32()
+        _check(lib().mwax_stream_poll(self.h, int(wait_ms), recs, max_records, ctypes.byref(n)))
+        return [recs[i].as_dict() for i in range(n.value)]
+
+    def vis_ptr(self, channel, j):
+        ptr = ctypes.c_void_p()
+        _check(lib().mwax_stream_vis(self.h, int(channel), int(j), ctypes.byref(ptr)))
+        return ptr.value
+
+
+def device_view(ptr, shape, dtype):
+    """A torch tensor over device memory owned by the library (no copy, no ownership)."""
+    import torch
+    n = 1
+    for d in shape:
+        n *= d
+    esize = torch.empty((), dtype=dtype).element_size()
+
+    class _Mem:
+        pass
+
+    typestr = {torch.int8: "|i1", torch.complex64: "<c8", torch.float32: "<f4", torch.int64: "<i8"}[dtype]
+    holder = _Mem()
+    holder.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
+                                       "version": 3, "strides": None}
+    assert n * esize > 0 and ptr
+    return torch.as_tensor(holder, device="cuda")
 
 
 def pair_index(n1, n2):

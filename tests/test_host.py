@@ -148,3 +148,42 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     out = ctypes.c_void_p()
     assert lib.mwax_plan_create(None, None, ctypes.byref(out)) == mwax.MWAX_E_INVAL
     assert out.value is None
+
+
+def test_batch_and_stream_arguments_are_checked_without_a_device(lib):
+    # every check below fails before the library touches the GPU
+    out = ctypes.c_void_p()
+    assert lib.mwax_batch_create(None, 0, None, ctypes.byref(out)) == mwax.MWAX_E_INVAL
+    fp32 = (mwax.Config * 2)(cfg(xprec="fp32"), cfg(xprec="fp32"))
+    assert lib.mwax_batch_create(fp32, 2, None, ctypes.byref(out)) == mwax.MWAX_E_UNSUPPORTED
+    mixed = (mwax.Config * 2)(cfg(xprec="int8"), cfg(xprec="fp16"))
+    assert lib.mwax_batch_create(mixed, 2, None, ctypes.byref(out)) == mwax.MWAX_E_UNSUPPORTED
+    bad = (mwax.Config * 2)(cfg(xprec="int8"), cfg(xprec="int8", n_tiles=0))
+    assert lib.mwax_batch_create(bad, 2, None, ctypes.byref(out)) == mwax.MWAX_E_INVAL
+    assert b"instance 1" in lib.mwax_last_error()
+    assert out.value is None
+    assert lib.mwax_batch_run(None, None, None, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_batch_destroy(None) == mwax.MWAX_OK
+
+    def stream_cfg(**kw):
+        base = dict(n_channels=2, out_depth=4, cfg=cfg(xprec="int8", max_samples=128 * 100),
+                    block_samples=128 * 400, hbm_budget_bytes=1 << 34)
+        base.update(kw)
+        return mwax.StreamConfig(base["n_channels"], base["out_depth"], base["cfg"],
+                                 base["block_samples"], base["hbm_budget_bytes"])
+
+    for kw in (dict(n_channels=0), dict(out_depth=0), dict(block_samples=128 * 450),
+               dict(hbm_budget_bytes=1000), dict(cfg=cfg(n_tiles=0))):
+        sc = stream_cfg(**kw)
+        assert lib.mwax_stream_create(ctypes.byref(sc), ctypes.byref(out)) == mwax.MWAX_E_INVAL, kw
+        assert out.value is None
+    assert lib.mwax_stream_create(None, ctypes.byref(out)) == mwax.MWAX_E_INVAL
+    n = ctypes.c_int32()
+    assert lib.mwax_stream_poll(None, 0, None, 0, ctypes.byref(n)) == mwax.MWAX_E_INVAL
+    assert lib.mwax_stream_destroy(None) == mwax.MWAX_OK
+
+
+def test_stream_struct_layouts():
+    assert ctypes.sizeof(mwax.StreamConfig) == 4 + 4 + ctypes.sizeof(mwax.Config) + 8 + 8
+    assert ctypes.sizeof(mwax.BlockDone) == 4 + 4 + 8 + 8 + 4 + 4 + 8 * 3
+    assert ctypes.sizeof(mwax.StreamInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 8
