@@ -62,7 +62,8 @@ def c4_instances():
 def cpu_baseline(volts, L, seconds, what):
     """The FP64 oracle (channelise + packed-triangle X-engine) timed on the host
     cores over the first spectra of ``volts`` (a device int8 [n][S][2] tensor),
-    the sample grown until it takes about ``seconds``."""
+    the sample grown until it takes about ``seconds``; then on one thread over a
+    smaller sample."""
     import oracle
     n_in = volts.shape[0]
     P = n_in * (n_in + 1) // 2
@@ -70,20 +71,45 @@ def cpu_baseline(volts, L, seconds, what):
     max_spec = min(2048, volts.shape[1] // L)
     v_host = volts[:, : max_spec * L].cpu().numpy()
 
-    def oracle_rate(n_spec):
+    def oracle_rate(n_spec, th):
         t0 = time.perf_counter()
         spec = oracle.channelise(v_host, L, nm=n_spec)
-        oracle.correlate(spec, n_spec, threads=threads)
+        oracle.correlate(spec, n_spec, threads=th)
         return time.perf_counter() - t0
 
-    n_spec = 4
-    dt = oracle_rate(n_spec)
-    while dt < 0.5 * seconds and n_spec < max_spec:
-        n_spec = int(min(max_spec, max(2 * n_spec, n_spec * seconds / max(dt, 1e-3))))
-        dt = oracle_rate(n_spec)
+    def grow(th, target):
+        n_spec = 2
+        dt = oracle_rate(n_spec, th)
+        while dt < 0.5 * target and n_spec < max_spec:
+            n_spec = int(min(max_spec, max(2 * n_spec, n_spec * target / max(dt, 1e-3))))
+            dt = oracle_rate(n_spec, th)
+        return n_spec, dt
+
+    n_spec, dt = grow(threads, seconds)
+    n1, dt1 = grow(1, seconds / 3)
     return {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
             "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
-                      f"({n_spec * L} samples) of {what}; FP64 FFT + packed triangle; {dt:.1f} s wall"}
+                      f"({n_spec * L} samples) of {what}; FP64 FFT + packed triangle; {dt:.1f} s wall",
+            "value_1_thread": P * n1 * L / dt1, "sample_1_thread": f"first {n1} spectra, {dt1:.1f} s wall"}
+
+
+def copy_bandwidth():
+    """Device-to-device copy rate (bytes read + written per second) of a 4 GiB
+    buffer, timed with HIP events: the practical HBM ceiling on this machine."""
+    import torch
+    src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def parse():
@@ -395,7 +421,9 @@ def main():
               "frac": round(x_achieved / x_peak, 4), "traffic": measured_traffic(f"xengine_{args.xprec}"),
               "avg_launch_ms": round(x_avg_ms, 4), "launches": x_n,
               "ops_per_launch": x_ops_launch}
+    copy_gbs = copy_bandwidth()
     roof_f = {"kernel": f"fengine_{args.xprec}", "bound": "hbm", "achieved": round(f_gbs, 1),
+              "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(f_gbs / copy_gbs, 4),
               "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(f_gbs / PEAK["hbm_gbs"], 4),
               "traffic": measured_traffic(f"fengine_{args.xprec}"),
               "avg_launch_ms": round(f_avg_ms, 4), "launches": f_n,

@@ -271,7 +271,11 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                         if constexpr (kTwReg) s = sc[i];
                         else s = a.inv_s[c];
                         const uint32_t br = quant8_bits(X.x, s), bi = quant8_bits(X.y, s);
-                        if (t == 0) {
+                        if constexpr (FPG == 1) {
+                            // one frame per group: the code's low byte goes straight out
+                            row[0] = (uint8_t)br;
+                            row[16] = (uint8_t)bi;
+                        } else if (t == 0) {
                             q0[2 * i] = br;
                             q0[2 * i + 1] = bi;
                         } else {
