@@ -128,7 +128,10 @@ struct FCfg {
     using SH = FftShape<L>;
     static constexpr int L1 = SH::L1, L2 = SH::L2, U = SH::U;
     static constexpr int G = PrecTraits<XP>::G, ES = PrecTraits<XP>::ES;
-    static constexpr int FPG = XP == MWAX_X_INT8 ? 2 : (XP == MWAX_X_FP16 && L <= 256 ? 2 : 1);
+    // INT8 at 16 <= L <= 512: one frame per group (byte writes) holds fewer
+    // registers than packing two frames' codes, for more waves per SIMD.
+    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 && L <= 512 ? 1 : 2)
+                                                 : (XP == MWAX_X_FP16 && L <= 256 ? 2 : 1);
     static constexpr int GPW = 64 / L2;
     static constexpr int NGWG = 4 * GPW;          // FFT groups per workgroup
     static constexpr int PACKS = G / FPG;         // frame packs per input
@@ -226,7 +229,14 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             __syncthreads();
         }
 
-        uint32_t q0[XP != MWAX_X_FP32 && FPG == 2 && !STATS ? 2 * L1 : 1];   // first frame of the pack
+        // first frame of the pack: binary16 bits per slot, or int8 codes packed four
+        // to a word (re words, then im words)
+        constexpr int kQ0 = XP == MWAX_X_INT8 ? 2 * ((L1 + 3) / 4) : 2 * L1;
+        uint32_t q0[XP != MWAX_X_FP32 && FPG == 2 && !STATS ? kQ0 : 1];
+        if constexpr (XP == MWAX_X_INT8 && FPG == 2 && !STATS) {
+#pragma unroll
+            for (int w = 0; w < kQ0; ++w) q0[w] = 0u;
+        }
         for (int t = 0; t < FPG; ++t) {
             const int f = pk * FPG + t;
             float2 v[L1];
@@ -275,13 +285,20 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                             // one frame per group: the code's low byte goes straight out
                             row[0] = (uint8_t)br;
                             row[16] = (uint8_t)bi;
-                        } else if (t == 0) {
-                            q0[2 * i] = br;
-                            q0[2 * i + 1] = bi;
                         } else {
-                            // low bytes of the two frames' codes -> one 16-bit write per half
-                            *reinterpret_cast<uint16_t *>(row) = (uint16_t)__builtin_amdgcn_perm(br, q0[2 * i], 0x0c0c0400u);
-                            *reinterpret_cast<uint16_t *>(row + 16) = (uint16_t)__builtin_amdgcn_perm(bi, q0[2 * i + 1], 0x0c0c0400u);
+                            // frame 0: keep the code's low byte in byte i % 4 of a word;
+                            // frame 1: pair it with the new code, one 16-bit write per half
+                            constexpr int kW = (L1 + 3) / 4;
+                            const int w = i / 4, p = i % 4;
+                            if (t == 0) {
+                                const uint32_t ins = 0x03020100u & ~(0xffu << (8 * p)) | (0x04u << (8 * p));
+                                q0[w] = __builtin_amdgcn_perm(br, q0[w], ins);
+                                q0[kW + w] = __builtin_amdgcn_perm(bi, q0[kW + w], ins);
+                            } else {
+                                const uint32_t pair = 0x0c0c0400u | (uint32_t)p;
+                                *reinterpret_cast<uint16_t *>(row) = (uint16_t)__builtin_amdgcn_perm(br, q0[w], pair);
+                                *reinterpret_cast<uint16_t *>(row + 16) = (uint16_t)__builtin_amdgcn_perm(bi, q0[kW + w], pair);
+                            }
                         }
                     } else if constexpr (XP == MWAX_X_FP16) {
                         const _Float16 hr = (_Float16)(X.x * a.half_scale), hi = (_Float16)(X.y * a.half_scale);
