@@ -108,7 +108,12 @@ struct XArgs {
     int32_t tile;           // tile edge (rows)
     void *integ;            // this slot's integrators [L][P][2] (int64 or double)
     int64_t P;
+    int32_t nks;            // chunks of row groups per tile (set by launch_xengine)
+    int32_t kchunk;         // row groups per chunk
 };
+// INT8 launches split every tile's row groups into chunks when that fills the
+// device's resident workgroup slots more evenly (chunks flush with exact int64
+// atomic adds); other precisions run whole segments.
 hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s);
 int xengine_tile(int xprec);
 

@@ -297,22 +297,37 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
     }
 }
 
+// Workgroup -> (channel, tile, chunk); the tiles and chunks of one channel are
+// consecutive, so they land on one XCD.
 template <int XP>
 __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
     __shared__ __align__(16) uint8_t lds[2 * kStage];
     const int nb = gridDim.x;
     const int lin = xcd_logical(blockIdx.x, nb);
-    const int c = lin / a.ntiles;
+    const int per_c = a.ntiles * a.nks;
+    const int c = lin / per_c;
+    const int rem = lin - c * per_c;
+    const int t = rem / a.nks, ks = rem - t * a.nks;
     int I, J;
-    tile_ij(lin - c * a.ntiles, I, J);
+    tile_ij(t, I, J);
     const int rowA0 = I * kTile, rowB0 = J * kTile;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wr = wave >> 1, wc = wave & 1;
+    XArgs b = a;
+    b.grp0 = a.grp0 + (int64_t)ks * a.kchunk;
+    b.ngrp = min(a.kchunk, a.ngrp - ks * a.kchunk);
     // A wave is idle on a diagonal tile above the diagonal, or when all its rows or
     // columns lie past the last input; it still stages data and meets the barriers.
     const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
-    if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
-    else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
+    if constexpr (XP == MWAX_X_INT8) {
+        if (a.nks > 1) {
+            if (idle) xengine_tile_loop<XP, false, true>(b, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, true, true>(b, lds, c, rowA0, rowB0, wr, wc);
+            return;
+        }
+    }
+    if (idle) xengine_tile_loop<XP, false>(b, lds, c, rowA0, rowB0, wr, wc);
+    else xengine_tile_loop<XP, true>(b, lds, c, rowA0, rowB0, wr, wc);
 }
 
 // Persistent batched form (see XBatchArgs): each workgroup takes items from the
@@ -493,8 +508,49 @@ __global__ __launch_bounds__(kF32Threads) void xengine_f32(XArgs a) {
 
 int xengine_tile(int) { return kTile; }
 
-hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s) {
-    const int64_t blocks = (int64_t)a.ntiles * a.L;
+namespace {
+// Resident workgroups of the single-plan MFMA kernel on the current device.
+int resident_slots() {
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(&xengine_mfma<MWAX_X_INT8>), kThreads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        slots = cus * per_cu;
+    }
+    return slots;
+}
+
+// Chunks per tile: the fewest that minimise the number of workgroup waves per
+// unit of work, with at least kMinChunkGroups row groups per chunk.
+constexpr int kMinChunkGroups = 64;
+int pick_chunks(int64_t items, int ngrp, int slots) {
+    int best = 1;
+    double best_cost = 1e300;
+    for (int k = 1; k <= 8; ++k) {
+        if (k > 1 && (ngrp + k - 1) / k < kMinChunkGroups) break;
+        const double waves = (double)((items * k + slots - 1) / slots);
+        const double cost = waves / k;
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = k;
+        }
+    }
+    return best;
+}
+}  // namespace
+
+hipError_t launch_xengine(int xprec, const XArgs &args, hipStream_t s) {
+    XArgs a = args;
+    a.nks = xprec == MWAX_X_INT8 ? pick_chunks((int64_t)a.ntiles * a.L, a.ngrp, resident_slots()) : 1;
+    a.kchunk = (a.ngrp + a.nks - 1) / a.nks;
+    a.nks = (a.ngrp + a.kchunk - 1) / a.kchunk;   // no empty chunk
+    const int64_t blocks = (int64_t)a.ntiles * a.L * a.nks;
     if (blocks <= 0 || a.ngrp <= 0) return hipSuccess;
     switch (xprec) {
         case MWAX_X_INT8:
