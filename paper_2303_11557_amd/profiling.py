@@ -55,12 +55,13 @@ def short_name(name):
 def kernel_key(name):
     """Stable key of a hot-path kernel ('fengine_int8', 'xengine_int8', ...), or None."""
     s = short_name(name)
-    m = re.match(r"fengine_kernel<(\d+), (\d), (false|true)>", s)
+    m = re.match(r"fengine_(batch_)?kernel<(\d+), (\d), (false|true)>", s)
     if m:
-        return f"fengine_{PREC[m.group(2)]}" + ("_stats" if m.group(3) == "true" else "")
-    m = re.match(r"xengine_mfma<(\d)>", s)
+        return (f"fengine_{'batch_' if m.group(1) else ''}{PREC[m.group(3)]}"
+                + ("_stats" if m.group(4) == "true" else ""))
+    m = re.match(r"xengine_(mfma|batch)<(\d)>", s)
     if m:
-        return f"xengine_{PREC[m.group(1)]}"
+        return f"xengine_{'batch_' if m.group(1) == 'batch' else ''}{PREC[m.group(2)]}"
     if s.startswith("xengine_f32"):
         return "xengine_fp32"
     if s.startswith("pack_"):
