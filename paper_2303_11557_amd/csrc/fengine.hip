@@ -108,7 +108,7 @@ __device__ __forceinline__ int chan_of(int r, int i) {
     return (k + L / 2) & (L - 1);
 }
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;   // default workgroup size (see FCfg::THREADS)
 
 // Output-image padding per channel (bytes beyond R * 32), chosen so the packed
 // output writes of a wave fall in distinct LDS banks.
@@ -118,7 +118,7 @@ constexpr int cp_pad(int L, int XP) {
                        : (L <= 256 ? (XP == MWAX_X_INT8 ? 4 : 8) : 4)));
 }
 
-// Work decomposition of one workgroup (4 waves, 256 threads) for length L and
+// Work decomposition of one workgroup (THREADS threads) for length L and
 // output precision XP.  An FFT group is L2 lanes; a wave holds GPW groups.
 // Each group transforms FPG consecutive frames of one input, so that the
 // results of FPG frames leave in one packed LDS write; the workgroup covers
@@ -130,10 +130,13 @@ struct FCfg {
     static constexpr int G = PrecTraits<XP>::G, ES = PrecTraits<XP>::ES;
     // INT8 at 16 <= L <= 512: one frame per group (byte writes) holds fewer
     // registers than packing two frames' codes, for more waves per SIMD.
-    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 && L <= 512 ? 1 : 2)
+    // INT8 at L >= 512 (16 or 32 lanes per FFT) takes eight waves, so that a
+    // workgroup still holds the 16 groups one frame per group needs.
+    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 ? 1 : 2)
                                                  : (XP == MWAX_X_FP16 && L <= 256 ? 2 : 1);
+    static constexpr int THREADS = XP == MWAX_X_INT8 && L >= 512 ? 512 : kThreads;
     static constexpr int GPW = 64 / L2;
-    static constexpr int NGWG = 4 * GPW;          // FFT groups per workgroup
+    static constexpr int NGWG = THREADS / 64 * GPW;   // FFT groups per workgroup
     static constexpr int PACKS = G / FPG;         // frame packs per input
     static constexpr int R = NGWG / PACKS;        // inputs per workgroup item
     static constexpr int CP = R * kRowBytes + cp_pad(L, XP);
@@ -141,8 +144,11 @@ struct FCfg {
     static constexpr int EXG = L + 8;             // exchange pitch per group (float2)
     static constexpr int OUT_BYTES = L * CP;
     static constexpr int STAGE_BYTES = L2 > 1 ? R * G * SP : 0;
-    static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * 8 : 0;
-    static constexpr int RED_BYTES = kThreads * L1 * 4;
+    // eight-wave workgroups exchange real and imaginary parts in two rounds
+    // through a float buffer (the float2 one would not fit the LDS)
+    static constexpr bool SPLIT_EX = THREADS > kThreads;
+    static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * (SPLIT_EX ? 4 : 8) : 0;
+    static constexpr int RED_BYTES = THREADS * L1 * 4;
     static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
 };
 
@@ -216,7 +222,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         __syncthreads();  // LDS of the previous item fully consumed
         if constexpr (L2 > 1) {
             constexpr int UPF = 2 * L / 16;
-            for (int u = tid; u < R * G * UPF; u += kThreads) {
+            for (int u = tid; u < R * G * UPF; u += C::THREADS) {
                 const int sl = u / (G * UPF);
                 const int rem = u - sl * G * UPF;
                 const int f = rem / UPF, o = rem - f * UPF;
@@ -336,19 +342,46 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                 }
                 // exchange through LDS; column swizzle r ^ (k1 / U) keeps both the
                 // writes (fixed k1) and the reads (fixed r2) free of bank conflicts
-                float2 *eg = ex + gg * EXG;
+                if constexpr (C::SPLIT_EX) {
+                    // real parts, then imaginary parts, through a float buffer
+                    float *ef = reinterpret_cast<float *>(ex) + gg * EXG;
+                    float2 wv[L1];
 #pragma unroll
-                for (int k1 = 0; k1 < L1; ++k1) eg[k1 * L2 + (r ^ (k1 / U))] = v[k1];
-                wave_sync();
+                    for (int k1 = 0; k1 < L1; ++k1) ef[k1 * L2 + (r ^ (k1 / U))] = v[k1].x;
+                    wave_sync();
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int k1 = r * U + u;
-                    float2 w[L2];
+                    for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[k1 * L2 + (r2 ^ r)];
-                    dft_regs<L2>(w, w2);
+                        for (int r2 = 0; r2 < L2; ++r2) wv[u * L2 + r2].x = ef[(r * U + u) * L2 + (r2 ^ r)];
+                    wave_sync();
 #pragma unroll
-                    for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2]);
+                    for (int k1 = 0; k1 < L1; ++k1) ef[k1 * L2 + (r ^ (k1 / U))] = v[k1].y;
+                    wave_sync();
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int r2 = 0; r2 < L2; ++r2) wv[u * L2 + r2].y = ef[(r * U + u) * L2 + (r2 ^ r)];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        dft_regs<L2>(wv + u * L2, w2);
+#pragma unroll
+                        for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, wv[u * L2 + k2]);
+                    }
+                } else {
+                    float2 *eg = ex + gg * EXG;
+#pragma unroll
+                    for (int k1 = 0; k1 < L1; ++k1) eg[k1 * L2 + (r ^ (k1 / U))] = v[k1];
+                    wave_sync();
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int k1 = r * U + u;
+                        float2 w[L2];
+#pragma unroll
+                        for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[k1 * L2 + (r2 ^ r)];
+                        dft_regs<L2>(w, w2);
+#pragma unroll
+                        for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2]);
+                    }
                 }
                 wave_sync();
             }
@@ -358,7 +391,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             __syncthreads();
             // store the image: per channel, nrows rows of 32 bytes, 16 bytes per thread
             const int units = L * nrows * 2;
-            for (int u = tid; u < units; u += kThreads) {
+            for (int u = tid; u < units; u += C::THREADS) {
                 const int c = u / (nrows * 2);
                 const int rem = u - c * nrows * 2;
                 const int sl = rem >> 1, h = rem & 1;
@@ -374,12 +407,12 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         // Deterministic reduction of the per-lane channel sums: lanes with the same r
         // hold the same channel set; sum them in a fixed order.
         __syncthreads();
-        float *red = reinterpret_cast<float *>(smem);   // [kThreads / L2 slots][L2][L1]
+        float *red = reinterpret_cast<float *>(smem);   // [THREADS / L2 slots][L2][L1]
 #pragma unroll
         for (int i = 0; i < L1; ++i) red[(gg * L2 + r) * L1 + i] = acc[i];
         __syncthreads();
-        constexpr int NSLOT = kThreads / L2;
-        for (int t = tid; t < L; t += kThreads) {
+        constexpr int NSLOT = C::THREADS / L2;
+        for (int t = tid; t < L; t += C::THREADS) {
             const int rr = t / L1, i = t - rr * L1;
             double sum = 0.0;
             for (int sl = 0; sl < NSLOT; ++sl) sum += (double)red[(sl * L2 + rr) * L1 + i];
@@ -389,7 +422,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 }
 
 template <int L, int XP, bool STATS>
-__global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
+__global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_kernel(FArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     fengine_body<L, XP, STATS>(a, blockIdx.x, gridDim.x, smem);
 }
@@ -397,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void fengine_kernel(FArgs a) {
 // Batched form: workgroups [block0[d], block0[d+1]) of the launch work on
 // descriptor d (a segment of one plan of the batch); the rest return at once.
 template <int L, int XP, bool STATS>
-__global__ __launch_bounds__(kThreads) void fengine_batch_kernel(FBatchArgs b) {
+__global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_batch_kernel(FBatchArgs b) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int nd = *b.ndesc;
     const int blk = blockIdx.x;
@@ -432,9 +465,9 @@ hipError_t launch_L(const FArgs &a, hipStream_t s) {
         attr_done[stats] = true;
     }
     if (stats)
-        hipLaunchKernelGGL((fengine_kernel<L, XP, true>), dim3((unsigned)grid), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((fengine_kernel<L, XP, true>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
     else
-        hipLaunchKernelGGL((fengine_kernel<L, XP, false>), dim3((unsigned)grid), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((fengine_kernel<L, XP, false>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
     return hipGetLastError();
 }
 
@@ -452,9 +485,9 @@ template <int L, int XP>
 hipError_t launch_batch_L(bool stats, const FBatchArgs &b, int grid, hipStream_t s) {
     const int lds = cfg_value_lds<L, XP>(stats);
     if (stats)
-        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, true>), dim3((unsigned)grid), dim3(kThreads), lds, s, b);
+        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, true>), dim3((unsigned)grid), dim3(FCfg<L, XP>::THREADS), lds, s, b);
     else
-        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, false>), dim3((unsigned)grid), dim3(kThreads), lds, s, b);
+        hipLaunchKernelGGL((fengine_batch_kernel<L, XP, false>), dim3((unsigned)grid), dim3(FCfg<L, XP>::THREADS), lds, s, b);
     return hipGetLastError();
 }
 
