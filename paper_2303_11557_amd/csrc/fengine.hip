@@ -149,6 +149,9 @@ struct FCfg {
     static constexpr bool SPLIT_EX = THREADS > kThreads;
     static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * (SPLIT_EX ? 4 : 8) : 0;
     static constexpr int RED_BYTES = THREADS * L1 * 4;
+    // load the next item's frames while transforming the current one (where the
+    // extra registers keep the occupancy)
+    static constexpr bool PREFETCH = XP == MWAX_X_INT8 && L2 > 1 && L <= 256;
     static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
 };
 
@@ -211,29 +214,64 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     for (int i = 0; i < (STATS ? L1 : 1); ++i) acc[i] = 0.0f;
     const float bias = 128.0f * (float)L;      // DC offset of the biased input
 
+    // Staging of the raw frames (two-pass split) through registers; with
+    // PREFETCH the global loads of the next item are issued before the current
+    // item is transformed, so their latency hides behind the FFT work.
+    constexpr int UPF = 2 * L / 16;                      // 16-byte units per frame
+    constexpr int NUNITS = L2 > 1 ? R * G * UPF : 0;
+    constexpr int NU = (NUNITS + C::THREADS - 1) / C::THREADS;
+    uint4 pre[NU > 0 ? NU : 1];
+    auto fetch = [&](int it) {
+        if constexpr (NU > 0) {
+            const int gs = it / nblk;
+            const int m0 = (it - gs * nblk) * R;
+            const int nr = min(R, a.n_in - m0);
+            const int64_t l0 = (int64_t)gs * G;
+            const int fv = (int)min((int64_t)G, a.nframes - l0);
+            const int64_t sf = a.frame0 + l0;
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                const int u = tid + j * C::THREADS;
+                const int sl = u / (G * UPF);
+                const int rem = u - sl * G * UPF;
+                const int f = rem / UPF, o = rem - f * UPF;
+                pre[j] = make_uint4(0u, 0u, 0u, 0u);     // frames past the end are zero
+                if (u < NUNITS && sl < nr && f < fv)
+                    pre[j] = *reinterpret_cast<const uint4 *>(
+                        a.volts + ((int64_t)(m0 + sl) * a.ld + (sf + f) * L) * 2 + o * 16);
+            }
+        }
+    };
+    if constexpr (C::PREFETCH) {
+        if (wg < items) fetch(wg);
+    }
+
     for (int item = wg; item < items; item += nwg) {
         const int gsel = item / nblk;
         const int n0 = (item - gsel * nblk) * R;
         const int nrows = min(R, a.n_in - n0);
-        const int64_t lf0 = (int64_t)gsel * G;
-        const int fvalid = (int)min((int64_t)G, a.nframes - lf0);
-        const int64_t src_frame = a.frame0 + lf0;
 
         __syncthreads();  // LDS of the previous item fully consumed
         if constexpr (L2 > 1) {
-            constexpr int UPF = 2 * L / 16;
-            for (int u = tid; u < R * G * UPF; u += C::THREADS) {
-                const int sl = u / (G * UPF);
-                const int rem = u - sl * G * UPF;
-                const int f = rem / UPF, o = rem - f * UPF;
-                uint4 val = make_uint4(0u, 0u, 0u, 0u);   // frames past the end are zero
-                if (sl < nrows && f < fvalid)
-                    val = *reinterpret_cast<const uint4 *>(
-                        a.volts + ((int64_t)(n0 + sl) * a.ld + (src_frame + f) * L) * 2 + o * 16);
-                *reinterpret_cast<uint4 *>(stage + (sl * G + f) * SP + o * 16) = val;
+            if constexpr (!C::PREFETCH) fetch(item);
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                const int u = tid + j * C::THREADS;
+                if (u < NUNITS) {
+                    const int sl = u / (G * UPF);
+                    const int rem = u - sl * G * UPF;
+                    const int f = rem / UPF, o = rem - f * UPF;
+                    *reinterpret_cast<uint4 *>(stage + (sl * G + f) * SP + o * 16) = pre[j];
+                }
             }
             __syncthreads();
+            if constexpr (C::PREFETCH) {
+                if (item + nwg < items) fetch(item + nwg);
+            }
         }
+        const int64_t lf0 = (int64_t)gsel * G;
+        const int fvalid = (int)min((int64_t)G, a.nframes - lf0);
+        const int64_t src_frame = a.frame0 + lf0;
 
         // first frame of the pack: binary16 bits per slot, or int8 codes packed four
         // to a word (re words, then im words)
