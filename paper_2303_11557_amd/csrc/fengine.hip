@@ -470,13 +470,15 @@ __global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_kernel(FArgs a
 template <int L, int XP, bool STATS>
 __global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_batch_kernel(FBatchArgs b) {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int nd = *b.ndesc;
+    // the tables are read through the constant address space (scalar loads)
+    const int nd = load_uniform(b.ndesc);
     const int blk = blockIdx.x;
-    if (blk >= b.block0[nd]) return;
+    if (blk >= load_uniform(b.block0 + nd)) return;
     int d = 0;
-    while (b.block0[d + 1] <= blk) ++d;
-    const FArgs a = b.desc[d];
-    fengine_body<L, XP, STATS>(a, blk - b.block0[d], b.block0[d + 1] - b.block0[d], smem);
+    while (load_uniform(b.block0 + d + 1) <= blk) ++d;
+    const FArgs a = load_uniform(b.desc + d);
+    const int first = load_uniform(b.block0 + d), count = load_uniform(b.block0 + d + 1) - first;
+    fengine_body<L, XP, STATS>(a, blk - first, count, smem);
 }
 
 template <int L, int XP>

@@ -59,6 +59,16 @@ hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count
                                hipStream_t s);
 hipError_t launch_copy_scales(const float *src, float *dst, int L, hipStream_t s);
 
+// Reads a workgroup-uniform table entry through the constant address space: the
+// compiler may then reload its fields where they are used (as it does for kernel
+// arguments) instead of holding them in registers for the whole kernel.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+    T v;
+    __builtin_memcpy(&v, (const __attribute__((address_space(4))) void *)p, sizeof(T));
+    return v;
+}
+
 // Batched F-engine: one launch covers the segments of many plans with the same
 // L and precision.  The tables live in device memory (they change per call while
 // the launch itself, grid included, is fixed and can be replayed from a graph).

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
     const int home = blockIdx.x & (kXQueues - 1);
     for (int v = 0; v < kXQueues; ++v) {
         const int q = (home + v) & (kXQueues - 1);
-        const int q0 = b.qbeg[q], qn = b.qbeg[q + 1] - q0;
+        const int q0 = load_uniform(b.qbeg + q), qn = load_uniform(b.qbeg + q + 1) - q0;
         for (;;) {
             if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[q * kXCounterStride], 1);
             __syncthreads();
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
             const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)b.items[q0 + k]);
             const int d = (int)(it >> 24), c = (int)((it >> 14) & 1023), t = (int)((it >> 6) & 255);
             const int ks = (int)(it & 63);
-            const XDesc xd = b.desc[d];
+            const XDesc xd = load_uniform(b.desc + d);
             XArgs a{};
             a.chan = xd.chan;
             a.NG = xd.NG;
