@@ -1,0 +1,152 @@
+"""Parity at the full sizes of the batch and streaming workloads, in the launch
+configuration the benchmark times (batch: autotuned, graph replay, 1 s calls;
+stream: device block pool, 8 s blocks, 1 s calls, 2 s integrations), on
+visibilities sampled over a handful of inputs that the FP64 oracle computes
+one by one.  Voltages are seeded and made on the device; the oracle sees the
+exact int8 samples the GPU consumed (copied back).
+
+INT8 checks, per sampled (channel, pair), relative to sqrt(V_aa V_bb):
+  * against the oracle's own INT8 chain -- its calibration over all inputs (the
+    rule of mwax_channelise), its requantisation of its FP64 spectra, its
+    integer X-engine -- below 2e-4: the chains differ only where an FP32 and an
+    FP64 spectrum fall on different sides of a rounding boundary;
+  * against FP64: below 1.25x the oracle INT8 chain's own error + 2e-4.  That
+    error is a property of the encoding, not of the GPU: a bin-centred tone
+    repeats its requantisation error in every spectrum, so it does not average
+    down with the integration length.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2303_11557_amd import mwax  # noqa: E402
+from paper_2303_11557_amd.mwax import Batch, Stream, device_view, make_config  # noqa: E402
+
+F_S = 1.28e6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    mwax.lib()
+    yield
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def pair_cols(sel):
+    """Global packed indices of the sampled pairs, in the oracle's local order."""
+    return [sel[a] * (sel[a] + 1) // 2 + sel[b] for a in range(len(sel)) for b in range(a + 1)]
+
+
+def check_int8(got, cal_rows, rows, sel, L, T, j, label):
+    """got: complex [L][npairs] GPU visibilities of integration j at the sampled
+    pairs; cal_rows: int8 [n_in][>= 131072][2] voltages of every input from the
+    start of integration j (the calibration window); rows: int8 [k][...][2]
+    voltages of the sampled inputs from the start of the block."""
+    ncal = min(T, -(-131072 // L))
+    _, s_o, inv_o = oracle.calibrate(oracle.channelise(cal_rows, L, nm=ncal))
+    spec = oracle.channelise(rows, L, m0=j * T, nm=T)
+    ref = oracle.correlate(spec, T, threads=8)[0]
+    vi = oracle.correlate_i64(oracle.requantise(spec, inv_o), T)[0].astype(np.float64)
+    v8 = (vi[..., 0] + 1j * vi[..., 1]) * (s_o.astype(np.float64) ** 2)[:, None]
+    k = len(sel)
+    auto = np.stack([ref[:, a * (a + 1) // 2 + a].real for a in range(k)], 1)
+    scale = np.stack([np.sqrt(np.abs(auto[:, a] * auto[:, b])) for a in range(k) for b in range(a + 1)], 1)
+    d_chain = float(np.max(np.abs(got - v8) / scale))
+    e_gpu = float(np.max(np.abs(got - ref) / scale))
+    e_chain = float(np.max(np.abs(v8 - ref) / scale))
+    log(f"{label}: vs oracle int8 chain {d_chain:.3g}; vs FP64 {e_gpu:.3g} (oracle int8 chain {e_chain:.3g})")
+    assert d_chain < 2e-4
+    assert e_gpu < 1.25 * e_chain + 2e-4
+
+
+def c4_instances():
+    tiles, lens, taus = (64, 128, 256), (32, 128, 1024), (0.5, 2.0, 8.0)
+    return [(tiles[i % 3], lens[(i // 3) % 3], taus[(i // 9) % 3]) for i in range(24)]
+
+
+def test_c4_batch_full_shape_sampled():
+    """The 24 uneven instances of the batch workload, one 1 s call, autotuned,
+    graph replay; the two 0.5 s integrations of three 256-tile instances
+    (L = 32, 128, 1024) checked on sampled inputs."""
+    inst = c4_instances()
+    chunk = int(F_S)
+    cfgs = [make_config(t, L=Lc, int_time_s=tau, xprec="int8", max_samples=chunk) for t, Lc, tau in inst]
+    volts = []
+    for i, (t, Lc, tau) in enumerate(inst):
+        v = torch.empty((2 * t, chunk, 2), dtype=torch.int8, device="cuda")
+        synth.device_volts(v, seed=synth.MWAX_SEED + 3 + (i << 16),
+                           sources=[synth.Source(3.0, (7 * i) % Lc - Lc // 2)], L=Lc)
+        volts.append(v)
+    torch.cuda.synchronize()
+    log("C4 full shape: voltages made")
+    check = {2: [1], 5: [1], 8: [0, 1]}     # 256 tiles, tau = 0.5 s, L = 32 / 128 / 1024
+    sel = [0, 1, 2, 130, 257, 400, 511]
+    cols = torch.tensor(pair_cols(sel), device="cuda")
+    host = {i: volts[i].cpu().numpy() for i in check}
+    got = {}
+    with Batch(cfgs) as b:
+        kc, grid = b.autotune(volts, trials=1)
+        log(f"C4 full shape: autotuned kchunk={kc} grid={grid}")
+        b.run(volts)
+        for i in check:
+            vis = b.plans[i].integrate(4)
+            assert vis.shape[0] == 2, f"instance {i}: {vis.shape[0]} integrations emitted"
+            got[i] = vis.index_select(2, cols).cpu().numpy().astype(np.complex128)
+        b.sync()
+    del volts
+    torch.cuda.empty_cache()
+    for i, js in check.items():
+        t, Lc, tau = inst[i]
+        T = int(round(tau * F_S / Lc))
+        for j in js:
+            check_int8(got[i][j], host[i][:, j * T * Lc:j * T * Lc + 131072], host[i][sel], sel, Lc, T, j,
+                       f"C4 instance {i} (L={Lc}) integration {j}")
+
+
+def test_c5_stream_full_shape_sampled():
+    """Two channels of the streaming workload (256 tiles, 8 s blocks, 1 s calls,
+    2 s integrations) through the device block pool; channel 0's second block
+    checked on sampled inputs (its integrations 4 .. 7)."""
+    n_tiles, L, tau = 256, 128, 2.0
+    block, call = int(8 * F_S), int(F_S)
+    n_in = 2 * n_tiles
+    T = int(round(tau * F_S / L))
+    cfg = make_config(n_tiles, L=L, int_time_s=tau, xprec="int8", max_samples=call)
+    sel = [0, 1, 5, 130, 300, 511]
+    cols = torch.tensor(pair_cols(sel), device="cuda")
+    with Stream(cfg, 2, block, 2 * n_in * block * 2, out_depth=6) as s:
+        host = None
+        for b, ch in ((0, 0), (0, 1), (1, 0)):
+            slot, ptr = s.acquire(-1)
+            view = device_view(ptr, (n_in, block, 2), torch.int8)
+            synth.device_volts(view, seed=synth.MWAX_SEED + 4 + ch, L=L, s0=b * block,
+                               sources=[synth.Source(2.0, 17)], stream=s.info.ingest_stream)
+            if (b, ch) == (1, 0):
+                torch.cuda.synchronize()
+                host = view.cpu().numpy()       # 10.5 GB: the calibration needs every input
+            s.submit(slot, ch, s.now())
+        recs = []
+        while len(recs) < 3:
+            recs += s.poll(-1)
+        log(f"C5 full shape: blocks done, latencies {[round(r['t_ready_s'] - r['t_arrival_s'], 3) for r in recs]}")
+        assert [r["n_ints"] for r in recs] == [4, 4, 4]
+        got = {}
+        for j in (4, 7):
+            ptr = s.vis_ptr(0, j)
+            v = device_view(ptr, (L, n_in * (n_in + 1) // 2), torch.complex64)
+            got[j] = v.index_select(1, cols).cpu().numpy().astype(np.complex128)
+    for j, g in got.items():
+        jl = j - 4                     # integration within the second block
+        check_int8(g, host[:, jl * T * L:jl * T * L + 131072], host[sel], sel, L, T, jl,
+                   f"C5 channel 0 integration {j}")
