@@ -131,9 +131,10 @@ struct FCfg {
     // INT8 at 16 <= L <= 512: one frame per group (byte writes) holds fewer
     // registers than packing two frames' codes, for more waves per SIMD.
     // INT8 at L >= 512 (16 or 32 lanes per FFT) takes eight waves, so that a
-    // workgroup still holds the 16 groups one frame per group needs.
-    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 ? 1 : 2)
-                                                 : (XP == MWAX_X_FP16 && L <= 256 ? 2 : 1);
+    // workgroup still holds the 16 groups one frame per group needs.  Binary16
+    // keeps one frame per group throughout (two would need 86 KB of LDS at
+    // L = 128, one workgroup per CU).
+    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 ? 1 : 2) : 1;
     static constexpr int THREADS = XP == MWAX_X_INT8 && L >= 512 ? 512 : kThreads;
     static constexpr int GPW = 64 / L2;
     static constexpr int NGWG = THREADS / 64 * GPW;   // FFT groups per workgroup
@@ -151,7 +152,7 @@ struct FCfg {
     static constexpr int RED_BYTES = THREADS * L1 * 4;
     // load the next item's frames while transforming the current one (where the
     // extra registers keep the occupancy)
-    static constexpr bool PREFETCH = XP == MWAX_X_INT8 && L2 > 1 && L <= 256;
+    static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && L <= 256;
     static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
 };
 
