@@ -99,8 +99,7 @@ struct MfmaT<MWAX_X_FP16> {
 
 // One workgroup = one channel x one 128 x 128 tile of the lower triangle.
 // Four waves in a 2 x 2 layout, 64 x 64 outputs (2 x 2 blocks of 32 x 32) each,
-// real and imaginary accumulators for every block (128 accumulator registers);
-// diagonal tiles split their ten lower blocks 3 / 2 / 2 / 3 (see WaveShape).
+// real and imaginary accumulators for every block (128 accumulator registers).
 // Two workgroups share a CU (two waves per SIMD), so one workgroup's barrier and
 // load latency is covered by the other's matrix work.  The K loop runs over
 // stages of kXG row groups, double-buffered in LDS: while the matrix cores work
@@ -114,30 +113,11 @@ constexpr int kGroupPitch = 2 * kHalfPitch;
 constexpr int kPanel = kXG * kGroupPitch;   // one panel (A, B or B2) of a stage
 constexpr int kStage = 3 * kPanel;
 
-// What one wave computes of its workgroup's tile, in 32 x 32 blocks starting at
-// row offset R0 and column offset C0 within the tile:
-//   kFull: 2 x 2 blocks (a 64 x 64 square);
-//   kTri : the three blocks on and below the diagonal of a 64 x 64 diagonal
-//          square, (0,0), (1,0), (1,1);
-//   kRow : one row of two blocks, (0,0), (0,1).
-// A diagonal tile has ten such blocks: waves 0 and 3 take kTri squares, waves 1
-// and 2 the two rows of the square below them, so no wave carries more than
-// three (a 2 x 2 layout would leave one wave idle and give the others four).
-enum WaveShape { kFull = 0, kTri = 1, kRow = 2 };
-template <int SH>
-struct ShapeT {
-    static constexpr int NA = SH == kRow ? 1 : 2;              // row fragments
-    static constexpr bool use(int mb, int nb) { return SH == kFull || (SH == kTri ? !(mb == 0 && nb == 1) : mb == 0); }
-    static constexpr int MF = 2 * (SH == kFull ? 4 : (SH == kTri ? 3 : 2));   // MFMAs per row group
-    static constexpr int RD = NA + 4;                            // fragment reads per row group
-};
-
 // ATOMIC: flush with int64 atomic adds (another workgroup may be flushing other
 // row groups of the same tile at the same time).
-template <int XP, bool ACTIVE, bool ATOMIC = false, int SH = kFull>
+template <int XP, bool ACTIVE, bool ATOMIC = false>
 __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, int c, int rowA0, int rowB0,
-                                                  int R0, int C0) {
-    using W = ShapeT<SH>;
+                                                  int wr, int wc) {
     static_assert(!ATOMIC || XP == MWAX_X_INT8, "atomic flushes are exact for integer partials only");
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
@@ -190,22 +170,20 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
         }
     };
 
-    acc_t re[W::NA][2], im[W::NA][2];
-    const int fa_off = half * kHalfPitch + (R0 + l32) * 16;
-    const int fb_off = half * kHalfPitch + (C0 + l32) * 16;
+    acc_t re[2][2], im[2][2];
+    const int fa_off = half * kHalfPitch + (wr * 64 + l32) * 16;
+    const int fb_off = half * kHalfPitch + (wc * 64 + l32) * 16;
 
     // One stage of matrix-core work from LDS buffer buf; the fragments of row
     // group k+1 are read while the MFMAs of group k run.
     auto compute = [&](int buf) {
         const uint8_t *st = lds + buf * kStage;
-        uint4 fa[2][W::NA], fb[2][2], fb2[2][2];
+        uint4 fa[2][2], fb[2][2], fb2[2][2];
         auto read = [&](int k, int slot) {
             const int ko = k * kGroupPitch;
 #pragma unroll
-            for (int m = 0; m < W::NA; ++m)
-                fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
-#pragma unroll
             for (int m = 0; m < 2; ++m) {
+                fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
                 fb[slot][m] = *reinterpret_cast<const uint4 *>(st + kPanel + ko + fb_off + m * 32 * 16);
                 fb2[slot][m] = *reinterpret_cast<const uint4 *>(st + 2 * kPanel + ko + fb_off + m * 32 * 16);
             }
@@ -216,27 +194,24 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
             if (k + 1 < kXG) read(k + 1, (k + 1) & 1);
             const int sl = k & 1;
 #pragma unroll
-            for (int mb = 0; mb < W::NA; ++mb)
+            for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
-                    if (!W::use(mb, nb2)) continue;
                     re[mb][nb2] = T::mma(fa[sl][mb], fb[sl][nb2], re[mb][nb2]);
                     im[mb][nb2] = T::mma(fa[sl][mb], fb2[sl][nb2], im[mb][nb2]);
                 }
         }
-        constexpr int kPair = W::RD < W::MF ? W::RD : W::MF;
-        __builtin_amdgcn_sched_group_barrier(0x100, W::RD, 0);     // reads, group 0
+        __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);         // reads, group 0
 #pragma unroll
         for (int k = 0; k + 1 < kXG; ++k) {
 #pragma unroll
-            for (int q = 0; q < kPair; ++q) {
+            for (int q = 0; q < 6; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one read of group k+1
             }
-            if constexpr (W::MF > kPair) __builtin_amdgcn_sched_group_barrier(0x008, W::MF - kPair, 0);
-            if constexpr (W::RD > kPair) __builtin_amdgcn_sched_group_barrier(0x100, W::RD - kPair, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, W::MF, 0);     // MFMAs, last group
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
     };
 
     using S0 = std::integral_constant<int, 0>;
@@ -265,7 +240,7 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
         const int s1 = min(nstages, s0 + T::kFlushGroups / kXG);
         if constexpr (ACTIVE) {
 #pragma unroll
-            for (int mb = 0; mb < W::NA; ++mb)
+            for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
                     re[mb][nb2] = acc_t{};
@@ -287,14 +262,14 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
             int fr0 = rowA0, fc0 = rowB0;
             asm volatile("" : "+s"(ibase), "+s"(fr0), "+s"(fc0));
 #pragma unroll
-            for (int mb = 0; mb < W::NA; ++mb)
+            for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
-                    if (!W::use(mb, nb2)) continue;
-                    const int n2 = fc0 + C0 + nb2 * 32 + l32;
+                    const int RB = wr * 2 + mb, CB = wc * 2 + nb2;
+                    const int n2 = fc0 + CB * 32 + l32;
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const int n1 = fr0 + R0 + mb * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
+                        const int n1 = fr0 + RB * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
                         if (n1 < a.n_in && n2 <= n1) {
                             const int64_t p = (int64_t)n1 * (n1 + 1) / 2 + n2;
                             if constexpr (ATOMIC) {
@@ -322,32 +297,6 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
     }
 }
 
-// This wave's part of tile (I, J): 64 x 64 squares on off-diagonal tiles, the
-// kTri / kRow split on diagonal tiles.  A wave whose rows or columns all lie past
-// the last input idles (it still stages data and meets the barriers).
-template <int XP, bool ATOMIC>
-__device__ __forceinline__ void run_tile(const XArgs &a, uint8_t *lds, int c, int I, int J, int wave) {
-    const int rowA0 = I * kTile, rowB0 = J * kTile;
-    int sh, R0, C0;
-    if (I != J) {
-        sh = kFull;
-        R0 = (wave >> 1) * 64;
-        C0 = (wave & 1) * 64;
-    } else if (wave == 0 || wave == 3) {
-        sh = kTri;
-        R0 = C0 = wave == 0 ? 0 : 64;
-    } else {
-        sh = kRow;
-        R0 = wave == 1 ? 64 : 96;
-        C0 = 0;
-    }
-    const bool idle = rowA0 + R0 >= a.n_in || rowB0 + C0 >= a.n_in;
-    if (idle) xengine_tile_loop<XP, false, ATOMIC, kFull>(a, lds, c, rowA0, rowB0, R0, C0);
-    else if (sh == kFull) xengine_tile_loop<XP, true, ATOMIC, kFull>(a, lds, c, rowA0, rowB0, R0, C0);
-    else if (sh == kTri) xengine_tile_loop<XP, true, ATOMIC, kTri>(a, lds, c, rowA0, rowB0, R0, C0);
-    else xengine_tile_loop<XP, true, ATOMIC, kRow>(a, lds, c, rowA0, rowB0, R0, C0);
-}
-
 // Workgroup -> (chunk, channel, tile): the tiles of one channel are consecutive,
 // so they land on one XCD and share its L2; the chunks of a tile read disjoint
 // row groups and run one after another (measured: 25 % less HBM traffic than
@@ -363,17 +312,24 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
     const int c = rem / a.ntiles, t = rem - c * a.ntiles;
     int I, J;
     tile_ij(t, I, J);
+    const int rowA0 = I * kTile, rowB0 = J * kTile;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
     XArgs b = a;
     b.grp0 = a.grp0 + (int64_t)ks * a.kchunk;
     b.ngrp = min(a.kchunk, a.ngrp - ks * a.kchunk);
+    // A wave is idle on a diagonal tile above the diagonal, or when all its rows or
+    // columns lie past the last input; it still stages data and meets the barriers.
+    const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
     if constexpr (XP == MWAX_X_INT8) {
         if (a.nks > 1) {
-            run_tile<XP, true>(b, lds, c, I, J, wave);
+            if (idle) xengine_tile_loop<XP, false, true>(b, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, true, true>(b, lds, c, rowA0, rowB0, wr, wc);
             return;
         }
     }
-    run_tile<XP, false>(b, lds, c, I, J, wave);
+    if (idle) xengine_tile_loop<XP, false>(b, lds, c, rowA0, rowB0, wr, wc);
+    else xengine_tile_loop<XP, true>(b, lds, c, rowA0, rowB0, wr, wc);
 }
 
 // Persistent batched form (see XBatchArgs): each workgroup takes items from the
@@ -385,6 +341,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
     __shared__ __align__(16) uint8_t lds[2 * kStage];
     __shared__ int s_item;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
     const int home = blockIdx.x & (kXQueues - 1);
     for (int v = 0; v < kXQueues; ++v) {
         const int q = (home + v) & (kXQueues - 1);
@@ -409,13 +366,17 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
             a.P = xd.P;
             int I, J;
             tile_ij(t, I, J);
+            const int rowA0 = I * kTile, rowB0 = J * kTile;
+            const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
             if constexpr (XP == MWAX_X_INT8) {
                 if (xd.ksplit > 1) {
-                    run_tile<XP, true>(a, lds, c, I, J, wave);
+                    if (idle) xengine_tile_loop<XP, false, true>(a, lds, c, rowA0, rowB0, wr, wc);
+                    else xengine_tile_loop<XP, true, true>(a, lds, c, rowA0, rowB0, wr, wc);
                     continue;
                 }
             }
-            run_tile<XP, false>(a, lds, c, I, J, wave);
+            if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
         }
     }
 }
