@@ -336,7 +336,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                             constexpr int kW = (L1 + 3) / 4;
                             const int w = i / 4, p = i % 4;
                             if (t == 0) {
-                                const uint32_t ins = 0x03020100u & ~(0xffu << (8 * p)) | (0x04u << (8 * p));
+                                const uint32_t ins = (0x03020100u & ~(0xffu << (8 * p))) | (0x04u << (8 * p));
                                 q0[w] = __builtin_amdgcn_perm(br, q0[w], ins);
                                 q0[kW + w] = __builtin_amdgcn_perm(bi, q0[kW + w], ins);
                             } else {
@@ -580,10 +580,6 @@ hipError_t launch_xp(int L, const FArgs &a, hipStream_t s) {
     }
 }
 
-int l2_of(int L) {
-    return L <= 16 ? 1 : (L == 32 ? 4 : (L <= 128 ? 8 : (L <= 512 ? 16 : 32)));
-}
-
 // ---------------------------------------------------------------------------
 __global__ void twiddle_kernel(float2 *tw, int L) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -612,7 +608,7 @@ __device__ void calib_finish_channel(const double *stats, int nwg, int L, double
     part[threadIdx.x] = t;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x != 0) return;

@@ -16,7 +16,7 @@
 // input.
 //
 //   INT8: v_mfma_i32_32x32x32_i8, int32 partials flushed to int64 integrators
-//         at most every 32768 spectra (|partial| <= 2 * 127^2 * 32768 < 2^31).
+//         at most every 65536 spectra (|partial| <= 2 * 127^2 * 65536 < 2^31).
 //   FP16: v_mfma_f32_32x32x16_f16, FP32 partials flushed to FP64 integrators.
 //   FP32: vector ALUs, 4 x 8 complex outputs per thread, two-level FP32
 //         partials (see xengine_f32) flushed to FP64 integrators every 2048
@@ -74,9 +74,10 @@ template <int XP>
 struct MfmaT;
 template <>
 struct MfmaT<MWAX_X_INT8> {
-    using acc_t = v16i;
-    static constexpr int G = 16;                 // spectra per row group
-    static constexpr int kFlushGroups = 2048;    // 32768 spectra
+    using acc_t = v16i;                          // 16 spectra per row group
+    // a row group adds at most 2 * 127^2 * 16 = 516128 to a partial, so 4096
+    // groups (65536 spectra) stay below 2^31
+    static constexpr int kFlushGroups = 4096;
     __device__ static acc_t mma(uint4 a, uint4 b, acc_t c) {
         v4i av, bv;
         __builtin_memcpy(&av, &a, 16);
@@ -86,8 +87,7 @@ struct MfmaT<MWAX_X_INT8> {
 };
 template <>
 struct MfmaT<MWAX_X_FP16> {
-    using acc_t = v16f;
-    static constexpr int G = 8;
+    using acc_t = v16f;                           // 8 spectra per row group
     static constexpr int kFlushGroups = 8192;     // 65536 spectra per FP32 partial
     __device__ static acc_t mma(uint4 a, uint4 b, acc_t c) {
         v8h av, bv;

@@ -222,3 +222,27 @@ def test_batch_slot_exhaustion_is_atomic(volts):
         r0, _ = b.plans[0].integrate_raw(64)
         r1, _ = b.plans[1].integrate_raw(64)
         assert r0.shape[0] == r1.shape[0] == k
+
+
+def test_batch_int8_whole_segment_partial_at_the_int32_bound():
+    """70,000 spectra of +-127 on every input in one whole-segment work item of the
+    persistent X-engine: the int32 partial reaches 2 * 127^2 * 65536 = 2.114e9
+    (just below 2^31) before its flush, and the int64 sums pass 2^31.  With L = 1
+    the transform is the identity and with scale 1 the codes are the samples, so
+    the oracle's integer X-engine on the same values is the reference."""
+    n_tiles, L, M = 2, 1, 70000
+    q = np.full((M, L, 4, 2), 127, np.int8)
+    q[:, :, 1, 1] = -127
+    q[::3, :, 2, 0] = -127
+    volts = torch.from_numpy(np.ascontiguousarray(q[:, 0].transpose(1, 0, 2))).cuda()   # [n][M][2]
+    with Batch([make_config(n_tiles, L=L, T=M, xprec="int8", max_samples=L * M)]) as b:
+        b.set_tuning([0], 0)                       # whole segments: one item of 4375 row groups
+        p = b.plans[0]
+        p.set_scales(np.ones(L, np.float32))
+        b.run([volts])
+        assert np.array_equal(p.read_channelised().cpu().numpy(), q)
+        raw, _ = p.integrate_raw(1)
+        raw = raw.cpu().numpy()
+    ref = oracle.correlate_i64(q, M)
+    assert np.abs(ref).max() > 2 ** 31
+    assert np.array_equal(raw, ref)
