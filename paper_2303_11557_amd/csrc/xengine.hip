@@ -16,7 +16,7 @@
 // input.
 //
 //   INT8: v_mfma_i32_32x32x32_i8, int32 partials flushed to int64 integrators
-//         at most every 65536 spectra (|partial| <= 2 * 127^2 * 65536 < 2^31).
+//         at most every 65536 spectra (|partial| < 518160 * 4096 < 2^31).
 //   FP16: v_mfma_f32_32x32x16_f16, FP32 partials flushed to FP64 integrators.
 //   FP32: vector ALUs, 4 x 8 complex outputs per thread, two-level FP32
 //         partials (see xengine_f32) flushed to FP64 integrators every 2048
@@ -75,8 +75,9 @@ struct MfmaT;
 template <>
 struct MfmaT<MWAX_X_INT8> {
     using acc_t = v16i;                          // 16 spectra per row group
-    // a row group adds at most 2 * 127^2 * 16 = 516128 to a partial, so 4096
-    // groups (65536 spectra) stay below 2^31
+    // a row group adds at most (127 * 128 + 127^2) * 16 = 518160 to a partial
+    // (the Im operand holds one's complements, see below), so 4096 groups
+    // (65536 spectra) stay below 2^31
     static constexpr int kFlushGroups = 4096;
     __device__ static acc_t mma(uint4 a, uint4 b, acc_t c) {
         v4i av, bv;
@@ -100,92 +101,109 @@ struct MfmaT<MWAX_X_FP16> {
 // One workgroup = one channel x one 128 x 128 tile of the lower triangle.
 // Four waves in a 2 x 2 layout, 64 x 64 outputs (2 x 2 blocks of 32 x 32) each,
 // real and imaginary accumulators for every block (128 accumulator registers).
-// Two workgroups share a CU (two waves per SIMD), so one workgroup's barrier and
-// load latency is covered by the other's matrix work.  The K loop runs over
-// stages of kXG row groups, double-buffered in LDS: while the matrix cores work
-// on stage s, the next stage's global loads are in flight; one barrier per stage.
-// Accumulators are flushed into the integrators after each chunk of at most
-// kFlushGroups groups.
+// Two workgroups share a CU (two waves per SIMD), so one workgroup's barrier
+// latency is covered by the other's matrix work.
+//
+// The K loop runs over stages of kXG row groups.  Stages are copied from global
+// memory straight into LDS (16 bytes per lane, no register staging and no LDS
+// store instructions) into a ring of kNBuf stage buffers, kNBuf - 1 stages
+// ahead of the matrix work, with one barrier per stage.  Each wave copies one
+// half (re or im) of 64 rows of both panels.  The ring buffers are separate LDS
+// objects, so the compiler can tell a read of one buffer from the copies still
+// landing in the others and does not wait for those.
+//
+// The Im operand B2 = [-im | re] is formed in registers: reading the other half
+// of the B panel swaps re and im, and the lanes that hold the imaginary half
+// flip it -- FP16 by its sign bit, INT8 by its one's complement ~x = -x - 1.
+// The INT8 form therefore yields Im V[n1,n2] - sum_m re_n1[m]; the row sums
+// sum_m re_n1[m] are accumulated alongside (dot products of the A fragments
+// with ones) and added back when the partial sums are flushed, so the result
+// stays exact.  With ~im in [-128, 126] a row group adds at most
+// 127 * 128 * 16 + 127^2 * 16 to a partial, and 65536 spectra stay below 2^31.
 constexpr int kXG = 2;                      // row groups per stage
-constexpr int kPF = 1;                      // stages of global loads in flight (1 or 2)
+constexpr int kNBuf = 4;                    // stage buffers (kNBuf - 1 stages in flight)
 constexpr int kHalfPitch = kTile * 16 + 64; // LDS bytes per half of a group (padded)
 constexpr int kGroupPitch = 2 * kHalfPitch;
-constexpr int kPanel = kXG * kGroupPitch;   // one panel (A, B or B2) of a stage
-constexpr int kStage = 3 * kPanel;
+constexpr int kPanel = kXG * kGroupPitch;   // one panel (A or B) of a stage
+constexpr int kStage = 2 * kPanel;
+constexpr int kCopiesPerStage = 2 * kXG;    // global -> LDS copies per wave per stage
+static_assert(kNBuf == 4 && kCopiesPerStage == 4, "stage_barrier waits for all but 2 stages of 4 copies");
+
+struct XLds {
+    uint8_t *buf[kNBuf];
+};
+
+// Source of the row groups past the end of a segment (they must read as zero).
+__device__ __align__(16) const uint8_t kZeroGroup[kTile * kRowBytes] = {};
+
+// End of a stage: this wave's copies of the next stage have landed (the two
+// later stages stay in flight) and its LDS reads have returned; then the
+// workgroup barrier.  The barrier carries no memory fence of its own (a fence
+// would wait for every copy in flight); the wait provides the ordering, and the
+// memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void stage_barrier() {
+    __builtin_amdgcn_s_waitcnt(0x0078);   // vmcnt(8) lgkmcnt(0)
+    asm volatile("s_barrier" ::: "memory");
+}
 
 // ATOMIC: flush with int64 atomic adds (another workgroup may be flushing other
 // row groups of the same tile at the same time).
 template <int XP, bool ACTIVE, bool ATOMIC = false>
-__device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, int c, int rowA0, int rowB0,
+__device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &lds, int c, int rowA0, int rowB0,
                                                   int wr, int wc) {
     static_assert(!ATOMIC || XP == MWAX_X_INT8, "atomic flushes are exact for integer partials only");
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
-    const int tid = threadIdx.x, lane = tid & 63;
+    constexpr bool INT8 = XP == MWAX_X_INT8;
+    const int lane = threadIdx.x & 63;
     const int half = lane >> 5, l32 = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 
-    // staging: thread t owns row t/2, half t%2 of each group, for both panels
-    const int srow = tid >> 1, sh = tid & 1;
-    const bool okA = rowA0 + srow < a.n_in, okB = rowB0 + srow < a.n_in;
+    // Copies: wave w moves half (w & 1) of rows (w >> 1) * 64 + lane of both
+    // panels.  Rows past the last input are read from a clamped (valid) address
+    // and not cleared: row i of A and column j of B reach only output (i, j), and
+    // outputs past the last input are never flushed.
+    const int chalf = wave & 1, crow = (wave >> 1) * 64 + lane;
+    const uint32_t offA = (uint32_t)min(rowA0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
+    const uint32_t offB = (uint32_t)min(rowB0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
+    const uint32_t offZ = (uint32_t)crow * kRowBytes + chalf * 16;
     const int64_t gstride = (int64_t)a.n_in * kRowBytes;   // bytes between row groups
     const uint8_t *base = a.chan + ((int64_t)c * a.NG + a.grp0) * gstride;
-    // Rows past the last input are loaded from a clamped (valid) address and not
-    // cleared: row i of A and column j of B reach only output (i, j), and outputs
-    // past the last input are never flushed.  Groups past the segment end must be
-    // zero; that test is uniform over the workgroup.
-    const uint8_t *pA = base + (int64_t)(okA ? rowA0 + srow : a.n_in - 1) * kRowBytes + sh * 16;
-    const uint8_t *pB = base + (int64_t)(okB ? rowB0 + srow : a.n_in - 1) * kRowBytes + sh * 16;
+    const int ldst = chalf * kHalfPitch + (wave >> 1) * 64 * 16;
     const int nstages = (a.ngrp + kXG - 1) / kXG;
-    const int lds_off = sh * kHalfPitch + srow * 16;
-    const int lds_off2 = (1 - sh) * kHalfPitch + srow * 16;
 
-    // kPF register sets of staged loads: stage k is loaded into set k % kPF at
-    // iteration k - 1 - kPF and written to LDS at iteration k - 1.
-    uint4 ra[kPF][kXG], rb[kPF][kXG];
-    auto load_stage = [&](int s, auto set_c) {
-        constexpr int set = decltype(set_c)::value;
+    // CHECK: the stage may reach past the segment end (its last stage)
+    auto copy_stage = [&](int s, uint8_t *buf, auto check_c) {
+        constexpr bool CHECK = decltype(check_c)::value;
 #pragma unroll
         for (int k = 0; k < kXG; ++k) {
             const int g = s * kXG + k;
-            if (g < a.ngrp) {
-                const int64_t off = (int64_t)g * gstride;
-                ra[set][k] = *reinterpret_cast<const uint4 *>(pA + off);
-                rb[set][k] = *reinterpret_cast<const uint4 *>(pB + off);
-            } else {
-                ra[set][k] = make_uint4(0u, 0u, 0u, 0u);
-                rb[set][k] = make_uint4(0u, 0u, 0u, 0u);
-            }
-        }
-    };
-    auto store_stage = [&](int buf, auto set_c) {
-        constexpr int set = decltype(set_c)::value;
-        uint8_t *st = lds + buf * kStage;
-#pragma unroll
-        for (int k = 0; k < kXG; ++k) {
-            const int ko = k * kGroupPitch;
-            *reinterpret_cast<uint4 *>(st + ko + lds_off) = ra[set][k];
-            *reinterpret_cast<uint4 *>(st + kPanel + ko + lds_off) = rb[set][k];
-            // B2 = [-im | re]: the re half goes to half 1, the negated im half to half 0
-            *reinterpret_cast<uint4 *>(st + 2 * kPanel + ko + lds_off2) = sh ? negate16<XP>(rb[set][k]) : rb[set][k];
+            const bool in = !CHECK || g < a.ngrp;
+            const uint8_t *gb = in ? base + (int64_t)g * gstride : kZeroGroup;
+            __builtin_amdgcn_global_load_lds(gb + (in ? offA : offZ), buf + k * kGroupPitch + ldst, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(gb + (in ? offB : offZ), buf + kPanel + k * kGroupPitch + ldst, 16, 0,
+                                             0);
         }
     };
 
     acc_t re[2][2], im[2][2];
+    int sre[2];                                   // INT8: row sums of the re codes (lanes 0..31)
     const int fa_off = half * kHalfPitch + (wr * 64 + l32) * 16;
-    const int fb_off = half * kHalfPitch + (wc * 64 + l32) * 16;
+    const int fb_off = kPanel + half * kHalfPitch + (wc * 64 + l32) * 16;
+    const int fb2_off = kPanel + (1 - half) * kHalfPitch + (wc * 64 + l32) * 16;
+    const uint32_t flip = half ? 0u : (INT8 ? 0xffffffffu : 0x80008000u);
 
-    // One stage of matrix-core work from LDS buffer buf; the fragments of row
-    // group k+1 are read while the MFMAs of group k run.
-    auto compute = [&](int buf) {
-        const uint8_t *st = lds + buf * kStage;
+    // One stage of matrix-core work from one buffer; the fragments of row group
+    // k+1 are read while the MFMAs of group k run.
+    auto compute = [&](const uint8_t *st) {
         uint4 fa[2][2], fb[2][2], fb2[2][2];
         auto read = [&](int k, int slot) {
             const int ko = k * kGroupPitch;
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
-                fb[slot][m] = *reinterpret_cast<const uint4 *>(st + kPanel + ko + fb_off + m * 32 * 16);
-                fb2[slot][m] = *reinterpret_cast<const uint4 *>(st + 2 * kPanel + ko + fb_off + m * 32 * 16);
+                fb[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb_off + m * 32 * 16);
+                fb2[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb2_off + m * 32 * 16);
             }
         };
         read(0, 0);
@@ -193,6 +211,18 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
         for (int k = 0; k < kXG; ++k) {
             if (k + 1 < kXG) read(k + 1, (k + 1) & 1);
             const int sl = k & 1;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                uint4 &v = fb2[sl][m];
+                v = make_uint4(v.x ^ flip, v.y ^ flip, v.z ^ flip, v.w ^ flip);
+                if constexpr (INT8) {
+                    const uint4 f = fa[sl][m];
+                    int t = __builtin_amdgcn_sdot4((int)f.x, 0x01010101, sre[m], false);
+                    t = __builtin_amdgcn_sdot4((int)f.y, 0x01010101, t, false);
+                    t = __builtin_amdgcn_sdot4((int)f.z, 0x01010101, t, false);
+                    sre[m] = __builtin_amdgcn_sdot4((int)f.w, 0x01010101, t, false);
+                }
+            }
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -214,46 +244,66 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
     };
 
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, (kPF > 1 ? 1 : 0)>;
-    load_stage(0, S0{});
-    store_stage(0, S0{});
-    __syncthreads();
-    if (nstages > 1) load_stage(1, S1{});
-    if constexpr (kPF > 1) {
-        if (nstages > 2) load_stage(2, S0{});
-    }
-
-    // one iteration: matrix work on stage s, LDS store of stage s+1 from its
-    // register set, loads of stage s+1+kPF into the set just freed
-    auto iteration = [&](int s, auto set_c) {
-        if constexpr (ACTIVE) compute(s & 1);
-        if (s + 1 < nstages) {
-            store_stage((s + 1) & 1, set_c);
-            if (s + 1 + kPF < nstages) load_stage(s + 1 + kPF, set_c);
+    // Iteration on stage s held in buffer B: copy stage s + kNBuf - 1 into the
+    // buffer read by the previous iteration, matrix work on stage s, wait for
+    // stage s + 1, barrier.  Every iteration copies a stage (past the segment end
+    // from the zero page), so exactly kCopiesPerStage copies per stage are in
+    // flight and no copy sits behind a branch: for a copy behind a branch the
+    // compiler would wait for every copy in flight before the next LDS read.
+    // CHECK: tail iterations, which may reach past the segment end and skip the
+    // matrix work of stages at or past s1.
+    using Yes = std::true_type;
+    using No = std::false_type;
+    auto iteration = [&](int s, int s1, auto b_c, auto check_c) {
+        constexpr int B = decltype(b_c)::value;
+        constexpr bool CHECK = decltype(check_c)::value;
+        copy_stage(s + kNBuf - 1, lds.buf[(B + kNBuf - 1) % kNBuf], check_c);
+        if constexpr (ACTIVE) {
+            if (!CHECK || s < s1) compute(lds.buf[B]);
         }
-        __syncthreads();
+        stage_barrier();
     };
-    static_assert((T::kFlushGroups / kXG) % 2 == 0, "flush chunks must hold an even number of stages");
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    using B2 = std::integral_constant<int, 2>;
+    using B3 = std::integral_constant<int, 3>;
 
-    for (int s0 = 0; s0 < nstages; s0 += T::kFlushGroups / kXG) {
-        const int s1 = min(nstages, s0 + T::kFlushGroups / kXG);
+    copy_stage(0, lds.buf[0], Yes{});
+    copy_stage(1, lds.buf[1], Yes{});
+    copy_stage(2, lds.buf[2], Yes{});
+    stage_barrier();
+
+    constexpr int kChunkStages = T::kFlushGroups / kXG;
+    static_assert(kChunkStages % kNBuf == 0, "flush chunks must start on buffer 0");
+    for (int s0 = 0; s0 < nstages; s0 += kChunkStages) {
+        // s1 is a multiple of kNBuf or the segment end
+        const int s1 = min(nstages, s0 + kChunkStages);
         if constexpr (ACTIVE) {
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < 2; ++mb) {
+                sre[mb] = 0;
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
                     re[mb][nb2] = acc_t{};
                     im[mb][nb2] = acc_t{};
                 }
+            }
         }
-        // s0 is even: stage s+1 of an even s sits in set S1, of an odd s in set S0
+        // steady state: every stage copied is whole and before the last one
+        const int sfull = min(s1, nstages - kNBuf);
         int s = s0;
-        for (; s + 1 < s1; s += 2) {
-            iteration(s, S1{});
-            iteration(s + 1, S0{});
+        for (; s + kNBuf <= sfull; s += kNBuf) {
+            iteration(s, s1, B0{}, No{});
+            iteration(s + 1, s1, B1{}, No{});
+            iteration(s + 2, s1, B2{}, No{});
+            iteration(s + 3, s1, B3{}, No{});
         }
-        if (s < s1) iteration(s, S1{});
+        for (; s < s1; s += kNBuf) {
+            iteration(s, s1, B0{}, Yes{});
+            iteration(s + 1, s1, B1{}, Yes{});
+            iteration(s + 2, s1, B2{}, Yes{});
+            iteration(s + 3, s1, B3{}, Yes{});
+        }
         if constexpr (ACTIVE) {
             // flush this chunk's partial sums into the integrators.  The base is made
             // opaque here so the compiler cannot hoist 64 integrator addresses out of
@@ -262,10 +312,17 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
             int fr0 = rowA0, fc0 = rowB0;
             asm volatile("" : "+s"(ibase), "+s"(fr0), "+s"(fc0));
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < 2; ++mb) {
+                const int RB = wr * 2 + mb;
+                int rs[16];
+                if constexpr (INT8) {
+                    // row sum of output row r of this lane, held by lane (row within the block)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) rs[r] = __shfl(sre[mb], (r >> 2) * 8 + half * 4 + (r & 3));
+                }
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
-                    const int RB = wr * 2 + mb, CB = wc * 2 + nb2;
+                    const int CB = wc * 2 + nb2;
                     const int n2 = fc0 + CB * 32 + l32;
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -276,12 +333,12 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
                                 unsigned long long *dst =
                                     reinterpret_cast<unsigned long long *>(ibase) + 2 * ((int64_t)c * a.P + p);
                                 atomicAdd(dst, (unsigned long long)(long long)re[mb][nb2][r]);
-                                atomicAdd(dst + 1, (unsigned long long)(long long)im[mb][nb2][r]);
-                            } else if constexpr (XP == MWAX_X_INT8) {
+                                atomicAdd(dst + 1, (unsigned long long)((long long)im[mb][nb2][r] + rs[r]));
+                            } else if constexpr (INT8) {
                                 longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
                                 longlong2 v = *dst;
                                 v.x += re[mb][nb2][r];
-                                v.y += im[mb][nb2][r];
+                                v.y += (long long)im[mb][nb2][r] + rs[r];
                                 *dst = v;
                             } else {
                                 double2 *dst = reinterpret_cast<double2 *>(ibase) + (int64_t)c * a.P + p;
@@ -293,8 +350,12 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
                         }
                     }
                 }
+            }
         }
     }
+    // the copies past the segment end must land before the LDS is reused (next
+    // work item) or released (workgroup end)
+    __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
 }
 
 // Workgroup -> (chunk, channel, tile): the tiles of one channel are consecutive,
@@ -303,7 +364,8 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, uint8_t *lds, 
 // interleaving them).
 template <int XP>
 __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
-    __shared__ __align__(16) uint8_t lds[2 * kStage];
+    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage], lds3[kStage];
+    const XLds lds{{lds0, lds1, lds2, lds3}};
     const int nb = gridDim.x;
     const int lin = xcd_logical(blockIdx.x, nb);
     const int per_k = a.ntiles * a.L;
@@ -338,8 +400,9 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
 // of row groups, run by the same loop as the single-plan kernel.
 template <int XP>
 __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
-    __shared__ __align__(16) uint8_t lds[2 * kStage];
+    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage], lds3[kStage];
     __shared__ int s_item;
+    const XLds lds{{lds0, lds1, lds2, lds3}};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int home = blockIdx.x & (kXQueues - 1);
