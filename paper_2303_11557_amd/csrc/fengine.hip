@@ -320,7 +320,8 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     acc[i] += X.x * X.x + X.y * X.y;
                 } else {
                     const int c = chan_of<L>(r, i);
-                    uint8_t *row = outbuf + c * CP + nl * kRowBytes + pk * FPG * ES;
+                    uint8_t *row = outbuf + c * CP + nl * kRowBytes + row_re_off(pk * FPG, ES);
+                    constexpr int IM = row_im_gap(ES);
                     if constexpr (XP == MWAX_X_INT8) {
                         float s;
                         if constexpr (kTwReg) s = sc[i];
@@ -329,7 +330,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                         if constexpr (FPG == 1) {
                             // one frame per group: the code's low byte goes straight out
                             row[0] = (uint8_t)br;
-                            row[16] = (uint8_t)bi;
+                            row[IM] = (uint8_t)bi;
                         } else {
                             // frame 0: keep the code's low byte in byte i % 4 of a word;
                             // frame 1: pair it with the new code, one 16-bit write per half
@@ -342,7 +343,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                             } else {
                                 const uint32_t pair = 0x0c0c0400u | (uint32_t)p;
                                 *reinterpret_cast<uint16_t *>(row) = (uint16_t)__builtin_amdgcn_perm(br, q0[w], pair);
-                                *reinterpret_cast<uint16_t *>(row + 16) = (uint16_t)__builtin_amdgcn_perm(bi, q0[kW + w], pair);
+                                *reinterpret_cast<uint16_t *>(row + IM) = (uint16_t)__builtin_amdgcn_perm(bi, q0[kW + w], pair);
                             }
                         }
                     } else if constexpr (XP == MWAX_X_FP16) {
@@ -355,15 +356,15 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                                 q0[2 * i + 1] = bi;
                             } else {
                                 *reinterpret_cast<uint32_t *>(row) = q0[2 * i] | (br << 16);
-                                *reinterpret_cast<uint32_t *>(row + 16) = q0[2 * i + 1] | (bi << 16);
+                                *reinterpret_cast<uint32_t *>(row + IM) = q0[2 * i + 1] | (bi << 16);
                             }
                         } else {
                             *reinterpret_cast<uint16_t *>(row + 2 * t) = (uint16_t)br;
-                            *reinterpret_cast<uint16_t *>(row + 16 + 2 * t) = (uint16_t)bi;
+                            *reinterpret_cast<uint16_t *>(row + IM + 2 * t) = (uint16_t)bi;
                         }
                     } else {
                         *reinterpret_cast<float *>(row) = X.x;
-                        *reinterpret_cast<float *>(row + 16) = X.y;
+                        *reinterpret_cast<float *>(row + IM) = X.y;
                     }
                 }
             };
@@ -665,6 +666,7 @@ __global__ void repack_kernel(RepackArgs a) {
         const int f = (int)(m % a.G);
         E *row = reinterpret_cast<E *>(a.chan + (((int64_t)c * a.NG + g) * a.n_in + n) * kRowBytes);
         E *cv = reinterpret_cast<E *>(a.canon) + (((a.m0 + m) * a.L + c) * (int64_t)a.n_in + n) * 2;
+        const int ire = row_re_off(f, ES) / ES, iim = ire + row_im_gap(ES) / ES;
         if (a.to_internal) {
             E re = E(0), im = E(0);
             if (m < a.nframes) {
@@ -675,11 +677,11 @@ __global__ void repack_kernel(RepackArgs a) {
                     if (im == (E)-128) im = (E)-127;
                 }
             }
-            row[f] = re;
-            row[a.G + f] = im;
+            row[ire] = re;
+            row[iim] = im;
         } else {
-            cv[0] = row[f];
-            cv[1] = row[a.G + f];
+            cv[0] = row[ire];
+            cv[1] = row[iim];
         }
     }
 }

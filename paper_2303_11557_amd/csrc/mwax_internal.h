@@ -14,6 +14,17 @@ namespace mwax {
 // the matrix cores read: one 16-byte half row per lane.
 constexpr int kRowBytes = 32;
 
+// Layout of one 32-byte row (G frames of one channel and input, elements of es
+// bytes).  INT8 (G = 16) and binary16 (G = 8): bytes 0..7 hold the real parts of
+// frames 0 .. G/2-1, bytes 8..15 their imaginary parts, bytes 16..31 the same for
+// frames G/2 .. G-1, so that each 16-byte half is one matrix-core operand that
+// carries both parts of its frames.  FP32 (G = 4): real parts 0..15, imaginary
+// parts 16..31.
+__host__ __device__ constexpr int row_re_off(int f, int es) {
+    return es == 4 ? f * 4 : f * es + (f * es >= 8 ? 8 : 0);
+}
+__host__ __device__ constexpr int row_im_gap(int es) { return es == 4 ? 16 : 8; }
+
 inline int group_of(int xprec) {
     return xprec == MWAX_X_INT8 ? 16 : (xprec == MWAX_X_FP16 ? 8 : 4);
 }

@@ -5,15 +5,16 @@
 // integration) in the packed lower-triangle order p = n1(n1+1)/2 + n2.
 //
 // The complex Hermitian rank-k update is run as two real GEMMs over the
-// channel-major rows [re_0..re_{G-1} | im_0..im_{G-1}] of each input:
-//   Re V[n1,n2] = sum (re1 re2 + im1 im2) = A_n1 . A_n2,   A = [re | im]
-//   Im V[n1,n2] = sum (im1 re2 - re1 im2) = A_n1 . B_n2,   B = [-im | re]
+// channel-major rows of each input (real and imaginary parts of G frames):
+//   Re V[n1,n2] = sum (re1 re2 + im1 im2) = A_n1 . A_n2,   A = the row
+//   Im V[n1,n2] = sum (im1 re2 - re1 im2) = A_n1 . B_n2,   B = the row with
+//                 each frame's (re, im) replaced by (-im, re)
 // so every complex multiply-accumulate is four real ones and nothing is
-// wasted on the real expansion.  B is built once per workgroup while staging
-// (negating the imaginary half), so the matrix cores read A, A and B straight
-// from LDS.  Work is split into 128 x 128 tiles of the lower triangle; waves
-// skip 32 x 32 blocks that lie wholly above the diagonal or past the last
-// input.
+// wasted on the real expansion.  Each 16-byte half of a row holds the real
+// parts of 8 (FP16: 4) frames followed by their imaginary parts, so B is made
+// from A in registers by swapping the two 8-byte quarters of a half and
+// negating one of them.  Work is split into 128 x 128 tiles of the lower
+// triangle.
 //
 //   INT8: v_mfma_i32_32x32x32_i8, int32 partials flushed to int64 integrators
 //         at most every 65536 spectra (|partial| < 518160 * 4096 < 2^31).
@@ -112,14 +113,15 @@ struct MfmaT<MWAX_X_FP16> {
 // objects, so the compiler can tell a read of one buffer from the copies still
 // landing in the others and does not wait for those.
 //
-// The Im operand B2 = [-im | re] is formed in registers: reading the other half
-// of the B panel swaps re and im, and the lanes that hold the imaginary half
-// flip it -- FP16 by its sign bit, INT8 by its one's complement ~x = -x - 1.
-// The INT8 form therefore yields Im V[n1,n2] - sum_m re_n1[m]; the row sums
-// sum_m re_n1[m] are accumulated alongside (dot products of the A fragments
-// with ones) and added back when the partial sums are flushed, so the result
-// stays exact.  With ~im in [-128, 126] a row group adds at most
-// 127 * 128 * 16 + 127^2 * 16 to a partial, and 65536 spectra stay below 2^31.
+// The Im operand B2 is formed in registers from the B fragment: its two 8-byte
+// quarters (real parts, imaginary parts of the same frames) are swapped and the
+// imaginary one is flipped -- FP16 by its sign bits, INT8 by its one's
+// complement ~x = -x - 1.  The INT8 form therefore yields Im V[n1,n2] -
+// sum_m re_n1[m]; the row sums sum_m re_n1[m] are accumulated alongside (dot
+// products of the A fragments' real quarter with ones) and added back when the
+// partial sums are flushed, so the result stays exact.  With ~im in [-128, 126]
+// a row group adds at most 127 * 128 * 16 + 127^2 * 16 to a partial, and 65536
+// spectra stay below 2^31.
 constexpr int kXG = 2;                      // row groups per stage
 constexpr int kNBuf = 4;                    // stage buffers (kNBuf - 1 stages in flight)
 constexpr int kHalfPitch = kTile * 16 + 64; // LDS bytes per half of a group (padded)
@@ -187,23 +189,21 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     };
 
     acc_t re[2][2], im[2][2];
-    int sre[2];                                   // INT8: row sums of the re codes (lanes 0..31)
+    int sre[2];                                   // INT8: row sums of the re codes (both halves)
     const int fa_off = half * kHalfPitch + (wr * 64 + l32) * 16;
     const int fb_off = kPanel + half * kHalfPitch + (wc * 64 + l32) * 16;
-    const int fb2_off = kPanel + (1 - half) * kHalfPitch + (wc * 64 + l32) * 16;
-    const uint32_t flip = half ? 0u : (INT8 ? 0xffffffffu : 0x80008000u);
+    constexpr uint32_t kFlip = INT8 ? 0xffffffffu : 0x80008000u;
 
     // One stage of matrix-core work from one buffer; the fragments of row group
     // k+1 are read while the MFMAs of group k run.
     auto compute = [&](const uint8_t *st) {
-        uint4 fa[2][2], fb[2][2], fb2[2][2];
+        uint4 fa[2][2], fb[2][2];
         auto read = [&](int k, int slot) {
             const int ko = k * kGroupPitch;
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
                 fb[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb_off + m * 32 * 16);
-                fb2[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb2_off + m * 32 * 16);
             }
         };
         read(0, 0);
@@ -211,16 +211,15 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         for (int k = 0; k < kXG; ++k) {
             if (k + 1 < kXG) read(k + 1, (k + 1) & 1);
             const int sl = k & 1;
+            uint4 fb2[2];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                uint4 &v = fb2[sl][m];
-                v = make_uint4(v.x ^ flip, v.y ^ flip, v.z ^ flip, v.w ^ flip);
+                const uint4 v = fb[sl][m];
+                fb2[m] = make_uint4(v.z ^ kFlip, v.w ^ kFlip, v.x, v.y);
                 if constexpr (INT8) {
                     const uint4 f = fa[sl][m];
-                    int t = __builtin_amdgcn_sdot4((int)f.x, 0x01010101, sre[m], false);
-                    t = __builtin_amdgcn_sdot4((int)f.y, 0x01010101, t, false);
-                    t = __builtin_amdgcn_sdot4((int)f.z, 0x01010101, t, false);
-                    sre[m] = __builtin_amdgcn_sdot4((int)f.w, 0x01010101, t, false);
+                    const int t = __builtin_amdgcn_sdot4((int)f.x, 0x01010101, sre[m], false);
+                    sre[m] = __builtin_amdgcn_sdot4((int)f.y, 0x01010101, t, false);
                 }
             }
 #pragma unroll
@@ -228,18 +227,18 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
                     re[mb][nb2] = T::mma(fa[sl][mb], fb[sl][nb2], re[mb][nb2]);
-                    im[mb][nb2] = T::mma(fa[sl][mb], fb2[sl][nb2], im[mb][nb2]);
+                    im[mb][nb2] = T::mma(fa[sl][mb], fb2[nb2], im[mb][nb2]);
                 }
         }
-        __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);         // reads, group 0
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);         // reads, group 0
 #pragma unroll
         for (int k = 0; k + 1 < kXG; ++k) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one read of group k+1
             }
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         }
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
     };
@@ -316,9 +315,11 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
                 const int RB = wr * 2 + mb;
                 int rs[16];
                 if constexpr (INT8) {
-                    // row sum of output row r of this lane, held by lane (row within the block)
+                    // row j of the block: lanes j and j + 32 hold the sums of its two halves;
+                    // output row r of this lane is row (r / 4) * 8 + half * 4 + r % 4
+                    const int tot = sre[mb] + __shfl_xor(sre[mb], 32);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) rs[r] = __shfl(sre[mb], (r >> 2) * 8 + half * 4 + (r & 3));
+                    for (int r = 0; r < 16; ++r) rs[r] = __shfl(tot, (r >> 2) * 8 + half * 4 + (r & 3));
                 }
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
