@@ -107,9 +107,10 @@ struct MfmaT<MWAX_X_FP16> {
 //
 // The K loop runs over stages of kXG row groups.  Stages are copied from global
 // memory straight into LDS (16 bytes per lane, no register staging and no LDS
-// store instructions) into a ring of kNBuf stage buffers, kNBuf - 1 stages
-// ahead of the matrix work, with one barrier per stage.  Each wave copies one
-// half (re or im) of 64 rows of both panels.  The ring buffers are separate LDS
+// store instructions) into a ring of kNBuf stage buffers, kDist stages
+// ahead of the matrix work, with one barrier per stage.  Each wave copies 32
+// whole rows (1 KB of global memory) of each panel into one LDS block laid out
+// [16-byte half][row], the layout the fragment reads want.  The ring buffers are separate LDS
 // objects, so the compiler can tell a read of one buffer from the copies still
 // landing in the others and does not wait for those.
 //
@@ -123,28 +124,34 @@ struct MfmaT<MWAX_X_FP16> {
 // a row group adds at most 127 * 128 * 16 + 127^2 * 16 to a partial, and 65536
 // spectra stay below 2^31.
 constexpr int kXG = 2;                      // row groups per stage
-constexpr int kNBuf = 4;                    // stage buffers (kNBuf - 1 stages in flight)
-constexpr int kHalfPitch = kTile * 16 + 64; // LDS bytes per half of a group (padded)
-constexpr int kGroupPitch = 2 * kHalfPitch;
+constexpr int kNBuf = 4;                    // stage buffers
+constexpr int kDist = 2;                    // stages copied ahead of the matrix work (< kNBuf)
+constexpr int kBlock = 32 * kRowBytes;      // LDS bytes of 32 rows: [half][row][16 B]
+constexpr int kGroupPitch = kTile / 32 * kBlock;
 constexpr int kPanel = kXG * kGroupPitch;   // one panel (A or B) of a stage
 constexpr int kStage = 2 * kPanel;
 constexpr int kCopiesPerStage = 2 * kXG;    // global -> LDS copies per wave per stage
-static_assert(kNBuf == 4 && kCopiesPerStage == 4, "stage_barrier waits for all but 2 stages of 4 copies");
+static_assert((kNBuf == 2 || kNBuf == 4) && kDist >= 1 && kDist < kNBuf, "ring of 2 or 4 stage buffers");
+// s_waitcnt immediate: vmcnt(copies of the kDist - 1 later stages), lgkmcnt(0)
+constexpr int kWaitCopies = kCopiesPerStage * (kDist - 1);
+static_assert(kWaitCopies < 16, "vmcnt immediate");
+constexpr int kStageWait = kWaitCopies | (7 << 4);
 
 struct XLds {
-    uint8_t *buf[kNBuf];
+    uint8_t *buf[4];   // the first kNBuf are used
 };
+constexpr int kStage23 = kNBuf > 2 ? kStage : 16;
 
 // Source of the row groups past the end of a segment (they must read as zero).
 __device__ __align__(16) const uint8_t kZeroGroup[kTile * kRowBytes] = {};
 
-// End of a stage: this wave's copies of the next stage have landed (the two
-// later stages stay in flight) and its LDS reads have returned; then the
+// End of a stage: this wave's copies of the next stage have landed (the
+// kDist - 1 later stages stay in flight) and its LDS reads have returned; then the
 // workgroup barrier.  The barrier carries no memory fence of its own (a fence
 // would wait for every copy in flight); the wait provides the ordering, and the
 // memory clobber keeps the compiler from moving LDS accesses across it.
 __device__ __forceinline__ void stage_barrier() {
-    __builtin_amdgcn_s_waitcnt(0x0078);   // vmcnt(8) lgkmcnt(0)
+    __builtin_amdgcn_s_waitcnt(kStageWait);
     asm volatile("s_barrier" ::: "memory");
 }
 
@@ -161,17 +168,18 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     const int half = lane >> 5, l32 = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 
-    // Copies: wave w moves half (w & 1) of rows (w >> 1) * 64 + lane of both
-    // panels.  Rows past the last input are read from a clamped (valid) address
-    // and not cleared: row i of A and column j of B reach only output (i, j), and
-    // outputs past the last input are never flushed.
-    const int chalf = wave & 1, crow = (wave >> 1) * 64 + lane;
+    // Copies: wave w moves rows w * 32 .. w * 32 + 31 of both panels; lane l
+    // takes half l / 32 of row w * 32 + l % 32 and lands at block w, byte l * 16.
+    // Rows past the last input are read from a clamped (valid) address and not
+    // cleared: row i of A and column j of B reach only output (i, j), and outputs
+    // past the last input are never flushed.
+    const int chalf = lane >> 5, crow = wave * 32 + (lane & 31);
     const uint32_t offA = (uint32_t)min(rowA0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
     const uint32_t offB = (uint32_t)min(rowB0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
     const uint32_t offZ = (uint32_t)crow * kRowBytes + chalf * 16;
     const int64_t gstride = (int64_t)a.n_in * kRowBytes;   // bytes between row groups
     const uint8_t *base = a.chan + ((int64_t)c * a.NG + a.grp0) * gstride;
-    const int ldst = chalf * kHalfPitch + (wave >> 1) * 64 * 16;
+    const int ldst = wave * kBlock;
     const int nstages = (a.ngrp + kXG - 1) / kXG;
 
     // CHECK: the stage may reach past the segment end (its last stage)
@@ -190,8 +198,10 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
 
     acc_t re[2][2], im[2][2];
     int sre[2];                                   // INT8: row sums of the re codes (both halves)
-    const int fa_off = half * kHalfPitch + (wr * 64 + l32) * 16;
-    const int fb_off = kPanel + half * kHalfPitch + (wc * 64 + l32) * 16;
+    // fragment m of a wave's 64 rows is block 2 * w + m; lane (half, l32) reads
+    // half `half` of its row l32
+    const int fa_off = wr * 2 * kBlock + half * 512 + l32 * 16;
+    const int fb_off = kPanel + wc * 2 * kBlock + half * 512 + l32 * 16;
     constexpr uint32_t kFlip = INT8 ? 0xffffffffu : 0x80008000u;
 
     // One stage of matrix-core work from one buffer; the fragments of row group
@@ -202,8 +212,8 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             const int ko = k * kGroupPitch;
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * 32 * 16);
-                fb[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb_off + m * 32 * 16);
+                fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * kBlock);
+                fb[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb_off + m * kBlock);
             }
         };
         read(0, 0);
@@ -243,8 +253,8 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
     };
 
-    // Iteration on stage s held in buffer B: copy stage s + kNBuf - 1 into the
-    // buffer read by the previous iteration, matrix work on stage s, wait for
+    // Iteration on stage s held in buffer B: copy stage s + kDist into a buffer
+    // last read by an earlier iteration, matrix work on stage s, wait for
     // stage s + 1, barrier.  Every iteration copies a stage (past the segment end
     // from the zero page), so exactly kCopiesPerStage copies per stage are in
     // flight and no copy sits behind a branch: for a copy behind a branch the
@@ -256,7 +266,7 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     auto iteration = [&](int s, int s1, auto b_c, auto check_c) {
         constexpr int B = decltype(b_c)::value;
         constexpr bool CHECK = decltype(check_c)::value;
-        copy_stage(s + kNBuf - 1, lds.buf[(B + kNBuf - 1) % kNBuf], check_c);
+        copy_stage(s + kDist, lds.buf[(B + kDist) % kNBuf], check_c);
         if constexpr (ACTIVE) {
             if (!CHECK || s < s1) compute(lds.buf[B]);
         }
@@ -267,9 +277,8 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     using B2 = std::integral_constant<int, 2>;
     using B3 = std::integral_constant<int, 3>;
 
-    copy_stage(0, lds.buf[0], Yes{});
-    copy_stage(1, lds.buf[1], Yes{});
-    copy_stage(2, lds.buf[2], Yes{});
+#pragma unroll
+    for (int b = 0; b < kDist; ++b) copy_stage(b, lds.buf[b], Yes{});
     stage_barrier();
 
     constexpr int kChunkStages = T::kFlushGroups / kXG;
@@ -289,19 +298,23 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             }
         }
         // steady state: every stage copied is whole and before the last one
-        const int sfull = min(s1, nstages - kNBuf);
+        const int sfull = min(s1, nstages - kDist - 1);
         int s = s0;
         for (; s + kNBuf <= sfull; s += kNBuf) {
             iteration(s, s1, B0{}, No{});
             iteration(s + 1, s1, B1{}, No{});
-            iteration(s + 2, s1, B2{}, No{});
-            iteration(s + 3, s1, B3{}, No{});
+            if constexpr (kNBuf > 2) {
+                iteration(s + 2, s1, B2{}, No{});
+                iteration(s + 3, s1, B3{}, No{});
+            }
         }
         for (; s < s1; s += kNBuf) {
             iteration(s, s1, B0{}, Yes{});
             iteration(s + 1, s1, B1{}, Yes{});
-            iteration(s + 2, s1, B2{}, Yes{});
-            iteration(s + 3, s1, B3{}, Yes{});
+            if constexpr (kNBuf > 2) {
+                iteration(s + 2, s1, B2{}, Yes{});
+                iteration(s + 3, s1, B3{}, Yes{});
+            }
         }
         if constexpr (ACTIVE) {
             // flush this chunk's partial sums into the integrators.  The base is made
@@ -365,7 +378,7 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
 // interleaving them).
 template <int XP>
 __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
-    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage], lds3[kStage];
+    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage23], lds3[kStage23];
     const XLds lds{{lds0, lds1, lds2, lds3}};
     const int nb = gridDim.x;
     const int lin = xcd_logical(blockIdx.x, nb);
@@ -401,7 +414,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
 // of row groups, run by the same loop as the single-plan kernel.
 template <int XP>
 __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
-    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage], lds3[kStage];
+    __shared__ __align__(16) uint8_t lds0[kStage], lds1[kStage], lds2[kStage23], lds3[kStage23];
     __shared__ int s_item;
     const XLds lds{{lds0, lds1, lds2, lds3}};
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
