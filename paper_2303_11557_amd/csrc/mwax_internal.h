@@ -131,6 +131,8 @@ struct XArgs {
     int64_t P;
     int32_t nks;            // chunks of row groups per tile (set by launch_xengine)
     int32_t kchunk;         // row groups per chunk
+    int32_t first;          // the segment starts its integration: a tile's first
+                            // non-atomic flush stores instead of adding
 };
 // INT8 launches split every tile's row groups into chunks when that fills the
 // device's resident workgroup slots more evenly (chunks flush with exact int64
@@ -156,6 +158,7 @@ struct XDesc {
     int32_t n_in;
     int32_t kchunk;         // row groups per chunk
     int32_t ksplit;         // chunks = ceil(ngrp / kchunk)
+    int32_t first;          // as XArgs::first
 };
 constexpr int kXBatchMaxDesc = 256;
 constexpr int kXBatchMaxTiles = 256;

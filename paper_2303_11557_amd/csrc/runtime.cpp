@@ -204,6 +204,7 @@ XArgs mwax::xengine_args(mwax_plan p, const Segment &s) {
     a.tile = xengine_tile(p->xprec);
     a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
     a.P = p->P;
+    a.first = s.local0 == 0;
     return a;
 }
 

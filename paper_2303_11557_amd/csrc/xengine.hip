@@ -323,6 +323,9 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             uint8_t *ibase = reinterpret_cast<uint8_t *>(a.integ);
             int fr0 = rowA0, fc0 = rowB0;
             asm volatile("" : "+s"(ibase), "+s"(fr0), "+s"(fc0));
+            // the first flush of a segment that starts its integration writes the
+            // integrators instead of adding to them (no read)
+            const bool store = a.first && s0 == 0;
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) {
                 const int RB = wr * 2 + mb;
@@ -350,15 +353,21 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
                                 atomicAdd(dst + 1, (unsigned long long)((long long)im[mb][nb2][r] + rs[r]));
                             } else if constexpr (INT8) {
                                 longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
-                                longlong2 v = *dst;
-                                v.x += re[mb][nb2][r];
-                                v.y += (long long)im[mb][nb2][r] + rs[r];
+                                longlong2 v = make_longlong2(re[mb][nb2][r], (long long)im[mb][nb2][r] + rs[r]);
+                                if (!store) {
+                                    const longlong2 o = *dst;
+                                    v.x += o.x;
+                                    v.y += o.y;
+                                }
                                 *dst = v;
                             } else {
                                 double2 *dst = reinterpret_cast<double2 *>(ibase) + (int64_t)c * a.P + p;
-                                double2 v = *dst;
-                                v.x += (double)re[mb][nb2][r];
-                                v.y += (double)im[mb][nb2][r];
+                                double2 v = make_double2((double)re[mb][nb2][r], (double)im[mb][nb2][r]);
+                                if (!store) {
+                                    const double2 o = *dst;
+                                    v.x += o.x;
+                                    v.y += o.y;
+                                }
                                 *dst = v;
                             }
                         }
@@ -441,6 +450,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
             a.n_in = xd.n_in;
             a.integ = xd.integ;
             a.P = xd.P;
+            a.first = xd.first;
             int I, J;
             tile_ij(t, I, J);
             const int rowA0 = I * kTile, rowB0 = J * kTile;
