@@ -160,6 +160,26 @@ int64_t eff_chunk(mwax_batch b, int i) {
 
 int nblk_of(mwax_plan p) { return (p->n_in + p->R - 1) / p->R; }
 
+// Whole-segment work items overwrite a slot with the first flush of each
+// integration, so emitting an integration need not clear its slot; chunked INT8
+// items add atomically and need cleared slots.  Slots emitted without clearing
+// are cleared when an instance switches to chunked items.
+mwax_status apply_clear_policy(mwax_batch b) {
+    for (int i = 0; i < b->n; ++i) {
+        mwax_plan p = b->inst[i];
+        const bool clear = b->kchunk[i] > 0;
+        if (clear && !p->clear_on_emit) {
+            for (int s = 0; s < p->nslots; ++s) {
+                if (p->slot_owner[s] != -1) continue;
+                hipError_t e = launch_fill_zero((uint8_t *)p->integ + (size_t)s * p->slot_bytes, p->slot_bytes, p->stream);
+                if (e != hipSuccess) return hip_fail(e, "slot clear");
+            }
+        }
+        p->clear_on_emit = clear;
+    }
+    return MWAX_OK;
+}
+
 // Table layout and buffers for the current tuning.
 mwax_status layout(mwax_batch b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);   // old tables may still be read
@@ -621,6 +641,7 @@ mwax_status mwax_batch_create(const mwax_config *cfgs, int32_t n, void *hip_stre
     b->xgrid_max = xengine_batch_max_grid(b->xprec, b->device);
     b->xgrid = b->xgrid_max;
     mwax_status st = layout(b);
+    if (st == MWAX_OK) st = apply_clear_policy(b);
     if (st != MWAX_OK) {
         free_batch(b);
         return st;
@@ -782,6 +803,7 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
         mwax_status r = mwax_reset(b->inst[i]);
         if (st2 == MWAX_OK) st2 = r;
     }
+    if (st2 == MWAX_OK) st2 = apply_clear_policy(b);
     hipError_t e = hipStreamSynchronize(b->stream);
     if (st != MWAX_OK) return st;
     if (st2 != MWAX_OK) return st2;
@@ -811,7 +833,8 @@ mwax_status mwax_batch_set_tuning(mwax_batch b, const int32_t *kchunk, int32_t g
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(MWAX_E_DEVICE, "stream synchronisation");
     if (kchunk) b->kchunk.assign(kchunk, kchunk + b->n);
     b->xgrid = grid == 0 ? b->xgrid_max : std::min(grid, 65535);
-    const mwax_status st = layout(b);
+    mwax_status st = layout(b);
+    if (st == MWAX_OK) st = apply_clear_policy(b);
     return st == MWAX_OK ? ok() : st;
 }
 

@@ -138,6 +138,10 @@ struct XArgs {
 // device's resident workgroup slots more evenly (chunks flush with exact int64
 // atomic adds); other precisions run whole segments.
 hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s);
+// True if launch_xengine adds every partial sum into the integrators (FP32, or
+// INT8 split into chunks); false if the first flush of a segment that starts
+// its integration overwrites them.
+bool xengine_accumulates(int xprec, const XArgs &a);
 int xengine_tile(int xprec);
 
 // Persistent batched X-engine.  A work item is one 128 x 128 tile of one channel
@@ -182,13 +186,14 @@ int xengine_batch_max_grid(int xprec, int device);   // resident workgroups on t
 // Integrate / pack
 // ---------------------------------------------------------------------------
 struct PackArgs {
-    void *integ;            // slot integrators [L][P][2], cleared after reading
+    void *integ;            // slot integrators [L][P][2], cleared after reading if clear
     int32_t is_int;         // int64 (1) or double (0) integrators
     const float *scales;    // INT8: s_c [L]; else NULL
     double post;            // FP16/FP32: multiply by this (2^(2e) or 1)
     void *out;              // complex64 or int64 output of this integration
     float *scales_out;      // raw mode: copy of s_c, may be NULL
     int32_t order;          // mwax_order; 2 = raw int64
+    int32_t clear;          // zero the integrators after reading them
     int32_t L;
     int32_t n_in;
     int64_t P;

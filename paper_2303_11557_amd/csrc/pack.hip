@@ -1,6 +1,7 @@
 // Integration output (Morrison et al. 2023, Sec. 2.5.2 and 2.7): turn one
 // completed integration's device integrators into the output visibilities and
-// clear them for reuse.  Done on the device rather than on the host CPU.
+// (unless the next integration in the slot overwrites them anyway) clear them
+// for reuse.  Done on the device rather than on the host CPU.
 //
 //   CHAN_TRI: out[c][p] = complex64(scale(V[c][p])), p = n1(n1+1)/2 + n2
 //   TILE_BL : out[bl][c][pp] for tile baselines a >= b (bl = a(a+1)/2 + b) and
@@ -32,11 +33,13 @@ __global__ void pack_tri_kernel(PackArgs a) {
         if (a.order == 2) {
             longlong2 *src = reinterpret_cast<longlong2 *>(a.integ) + t;
             reinterpret_cast<longlong2 *>(a.out)[t] = *src;
-            *src = make_longlong2(0, 0);
+            if (a.clear) *src = make_longlong2(0, 0);
         } else {
             reinterpret_cast<float2 *>(a.out)[t] = scaled(a, t, c);
-            if (a.is_int) reinterpret_cast<longlong2 *>(a.integ)[t] = make_longlong2(0, 0);
-            else reinterpret_cast<double2 *>(a.integ)[t] = make_double2(0.0, 0.0);
+            if (a.clear) {
+                if (a.is_int) reinterpret_cast<longlong2 *>(a.integ)[t] = make_longlong2(0, 0);
+                else reinterpret_cast<double2 *>(a.integ)[t] = make_double2(0.0, 0.0);
+            }
         }
     }
     if (a.scales_out) {
@@ -106,7 +109,7 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
         const int64_t total = nt * (nt + 1) / 2 * a.L * 4;
         hipLaunchKernelGGL(pack_tilebl_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || !a.clear) return e;
         return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
     }
     hipLaunchKernelGGL(pack_tri_kernel, dim3(grid_for((int64_t)a.L * a.P)), dim3(256), 0, s, a);

@@ -56,6 +56,11 @@ struct mwax_plan_s {
     int64_t next_emit = 0;
     bool fixed_mode = false;
     bool in_batch = false;          // owned by a batch or stream (destroyed with it)
+    // Clear a slot's integrators when its integration is emitted.  Off only where
+    // every integration's first X-engine flush overwrites the whole slot
+    // (whole-segment INT8/FP16 work of a batch); mwax_correlate clears a slot
+    // itself before accumulating into one that was not cleared.
+    bool clear_on_emit = true;
 
     bool timing = false;
     struct Ev { hipEvent_t a, b; int fam; };

@@ -438,6 +438,11 @@ mwax_status mwax_correlate(mwax_plan p) {
     if (!p->pending) return fail(MWAX_E_STATE, "no fresh channelised block to correlate");
     for (const Segment &s : p->segs) {
         const XArgs a = xengine_args(p, s);
+        if (s.local0 == 0 && !p->clear_on_emit && xengine_accumulates(p->xprec, a)) {
+            // this launch adds into a slot that was not cleared when it was last emitted
+            hipError_t e = launch_fill_zero(a.integ, p->slot_bytes, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "slot clear");
+        }
         hipError_t e = timed(p, 1, [&] { return launch_xengine(p->xprec, a, p->stream); });
         if (e != hipSuccess) return hip_fail(e, "X-engine launch");
         p->slot_count[s.slot] += s.nframes;
@@ -464,6 +469,7 @@ static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_i
         a.out = (uint8_t *)d_vis + (size_t)n * per_int * esz;
         a.scales_out = d_scales ? d_scales + (size_t)n * p->L : nullptr;
         a.order = order;
+        a.clear = p->clear_on_emit;
         a.L = p->L;
         a.n_in = p->n_in;
         a.P = p->P;

@@ -634,11 +634,25 @@ int pick_chunks(int64_t items, int ngrp, int slots) {
 }
 }  // namespace
 
-hipError_t launch_xengine(int xprec, const XArgs &args, hipStream_t s) {
-    XArgs a = args;
+namespace {
+// Chunks per tile of a single-plan launch (INT8 only) and their size.
+void set_chunks(int xprec, XArgs &a) {
     a.nks = xprec == MWAX_X_INT8 ? pick_chunks((int64_t)a.ntiles * a.L, a.ngrp, resident_slots()) : 1;
     a.kchunk = (a.ngrp + a.nks - 1) / a.nks;
     a.nks = (a.ngrp + a.kchunk - 1) / a.kchunk;   // no empty chunk
+}
+}  // namespace
+
+bool xengine_accumulates(int xprec, const XArgs &args) {
+    if (xprec == MWAX_X_FP32) return true;
+    XArgs a = args;
+    set_chunks(xprec, a);
+    return a.nks > 1;
+}
+
+hipError_t launch_xengine(int xprec, const XArgs &args, hipStream_t s) {
+    XArgs a = args;
+    set_chunks(xprec, a);
     const int64_t blocks = (int64_t)a.ntiles * a.L * a.nks;
     if (blocks <= 0 || a.ngrp <= 0) return hipSuccess;
     switch (xprec) {

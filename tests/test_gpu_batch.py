@@ -246,3 +246,35 @@ def test_batch_int8_whole_segment_partial_at_the_int32_bound():
     ref = oracle.correlate_i64(q, M)
     assert np.abs(ref).max() > 2 ** 31
     assert np.array_equal(raw, ref)
+
+
+def test_batch_slots_emitted_without_clearing_are_cleared_before_atomic_use():
+    """Whole-segment items overwrite a slot with their first flush, so emitting
+    does not clear it.  Work that adds atomically into such a slot must find it
+    cleared: (a) after switching the batch to chunked items, (b) when a batch
+    instance is driven through the single-plan path, whose 128-group segments
+    are split into chunks.  Both must equal the plan driven alone."""
+    call = 65536                                    # one integration per call, 128 row groups
+    shape = [(3, 32, call // 32)]
+    with Plan(cfgs("int8", shape, call)[0]) as q:
+        nslots = q.dims.n_slots
+    ncalls = 2 * nslots + 2
+    v = make_volts(20, 6, call * ncalls)
+    ref = run_single("int8", [v], shape, call, ncalls)[0]
+    for mode in ("retune", "single"):
+        got = []
+        with Batch(cfgs("int8", shape, call)) as b:
+            p = b.plans[0]
+            for k in range(ncalls):
+                chunk = v[:, k * call:(k + 1) * call]
+                if k == nslots and mode == "retune":
+                    b.set_tuning([64], 0)           # chunked items from here on
+                if k >= nslots and mode == "single":
+                    p.channelise(chunk)
+                    p.correlate()
+                else:
+                    b.run([chunk])
+                got.append(drain(p, "int8"))
+            b.sync()
+        log(f"{mode}: {ncalls} integrations, {nslots} slots")
+        assert_same([got], [ref], f"batch ({mode}) vs single")
