@@ -21,11 +21,22 @@
 namespace mwax {
 namespace {
 
-template <int L>
+// Two-pass split L = L1 * L2 over an FFT group of L2 lanes.  Pass 2 (length L2)
+// is done by each lane on U columns when L2 <= L1.  INT8 at L >= 512 keeps 16
+// points per lane (L2 = 32 or 64 > L1 = 16): each pass-2 transform is shared by
+// P = L2 / 16 neighbouring lanes, an in-lane 16-point DFT and then log2 P
+// radix-2 stages across the lanes (see fengine_body).  Measured: 1.2x (L = 1024)
+// and 1.1x (L = 512) over 32 points per lane for INT8, 0.9x for binary16, whose
+// 32-point kernels do not spill.
+template <int L, int XP>
 struct FftShape {
-    static constexpr int L2 = L <= 16 ? 1 : (L == 32 ? 4 : (L <= 128 ? 8 : (L <= 512 ? 16 : 32)));
+    static constexpr bool kLaneSplit = XP == MWAX_X_INT8 && L >= 512;
+    static constexpr int L2 = L <= 16 ? 1
+                              : (L == 32 ? 4
+                              : (L <= 128 ? 8 : (L == 256 ? 16 : (kLaneSplit ? L / 16 : (L == 512 ? 16 : 32)))));
     static constexpr int L1 = L / L2;
-    static constexpr int U = (L2 > 1) ? L1 / L2 : 1;
+    static constexpr int P = L2 > L1 ? L2 / L1 : 1;
+    static constexpr int U = (L2 > 1 && P == 1) ? L1 / L2 : 1;
 };
 
 template <int N>
@@ -98,14 +109,29 @@ template <>
 struct PrecTraits<MWAX_X_FP32> { static constexpr int G = 4, ES = 4; };
 
 // Channel of output slot i of lane r (see the kernel comment): bin
-// k = (r U + u) + L1 k2 with i = u L2 + k2, channel (k + L/2) mod L.
-template <int L>
+// k = (r U + u) + L1 k2 with i = u L2 + k2; with P lanes per pass-2 transform,
+// lane r = k1 P + h holds k = k1 + L1 (i + L1 bitrev_P(h)).  Channel (k + L/2) mod L.
+template <int L, int XP>
 __device__ __forceinline__ int chan_of(int r, int i) {
-    using SH = FftShape<L>;
+    using SH = FftShape<L, XP>;
     int k;
-    if constexpr (SH::L2 > 1) k = (r * SH::U + i / SH::L2) + SH::L1 * (i % SH::L2);
+    if constexpr (SH::P > 1) k = r / SH::P + SH::L1 * (i + SH::L1 * bitrev<SH::P>(r % SH::P));
+    else if constexpr (SH::L2 > 1) k = (r * SH::U + i / SH::L2) + SH::L1 * (i % SH::L2);
     else k = i;
     return (k + L / 2) & (L - 1);
+}
+
+// One radix-2 decimation-in-frequency stage across lanes h and h ^ B of a quad:
+// the lower lane keeps self + partner, the upper one partner - self (sgn = -1).
+template <int B, int N>
+__device__ __forceinline__ void lane_dif_stage(float2 *w, float sgn) {
+    constexpr int kCtrl = B == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const float px = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w[m].x), kCtrl, 0xf, 0xf, false));
+        const float py = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w[m].y), kCtrl, 0xf, 0xf, false));
+        w[m] = make_float2(fmaf(sgn, w[m].x, px), fmaf(sgn, w[m].y, py));
+    }
 }
 
 constexpr int kThreads = 256;   // default workgroup size (see FCfg::THREADS)
@@ -125,30 +151,30 @@ constexpr int cp_pad(int L, int XP) {
 // R inputs x G frames (one 32-byte row group per channel and input).
 template <int L, int XP>
 struct FCfg {
-    using SH = FftShape<L>;
+    using SH = FftShape<L, XP>;
     static constexpr int L1 = SH::L1, L2 = SH::L2, U = SH::U;
     static constexpr int G = PrecTraits<XP>::G, ES = PrecTraits<XP>::ES;
-    // INT8 at 16 <= L <= 512: one frame per group (byte writes) holds fewer
-    // registers than packing two frames' codes, for more waves per SIMD.
-    // INT8 at L >= 512 (16 or 32 lanes per FFT) takes eight waves, so that a
-    // workgroup still holds the 16 groups one frame per group needs.  Binary16
-    // keeps one frame per group throughout (two would need 86 KB of LDS at
-    // L = 128, one workgroup per CU).
-    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 ? 1 : 2) : 1;
-    static constexpr int THREADS = XP == MWAX_X_INT8 && L >= 512 ? 512 : kThreads;
+    // INT8 at 16 <= L <= 256: one frame per group (byte writes) holds fewer
+    // registers than packing two frames' codes, for more waves per SIMD.  At
+    // L >= 512 (32 or 64 lanes per FFT) an INT8 group transforms two frames,
+    // so that a workgroup still covers the 16 frames of a row group, and
+    // L = 1024 (one FFT per wave) takes eight waves.  Binary16 keeps one frame
+    // per group (two would need 86 KB of LDS at L = 128, one workgroup per CU).
+    static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 && L <= 256 ? 1 : 2) : 1;
+    static constexpr int THREADS = L == 1024 && XP == MWAX_X_INT8 ? 512 : kThreads;
+    static constexpr int P = SH::P;
     static constexpr int GPW = 64 / L2;
     static constexpr int NGWG = THREADS / 64 * GPW;   // FFT groups per workgroup
     static constexpr int PACKS = G / FPG;         // frame packs per input
     static constexpr int R = NGWG / PACKS;        // inputs per workgroup item
     static constexpr int CP = R * kRowBytes + cp_pad(L, XP);
     static constexpr int SP = 2 * L + 16;         // staged frame pitch (bytes)
-    static constexpr int EXG = L + 8;             // exchange pitch per group (float2)
+    // exchange area per group (float2): L + 8, or L1 rows of L2 + P (P > 1)
+    static constexpr int EXR = L2 + P;
+    static constexpr int EXG = P > 1 ? L1 * EXR : L + 8;
     static constexpr int OUT_BYTES = L * CP;
     static constexpr int STAGE_BYTES = L2 > 1 ? R * G * SP : 0;
-    // eight-wave workgroups exchange real and imaginary parts in two rounds
-    // through a float buffer (the float2 one would not fit the LDS)
-    static constexpr bool SPLIT_EX = THREADS > kThreads;
-    static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * (SPLIT_EX ? 4 : 8) : 0;
+    static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * 8 : 0;
     static constexpr int RED_BYTES = THREADS * L1 * 4;
     // load the next item's frames while transforming the current one (where the
     // extra registers keep the occupancy)
@@ -195,20 +221,29 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     // Per-lane constants.  Output slot i of a lane (i = u * L2 + k2 for the
     // two-pass split) holds FFT bin k = (r U + u) + L1 k2, channel (k + L/2) mod L.
     constexpr bool kTwReg = L1 <= 16;
-    float2 w1[L1 / 2 > 0 ? L1 / 2 : 1], w2[L2 / 2 > 0 ? L2 / 2 : 1];
+    constexpr int P = C::P;
+    constexpr int NW2 = P == 1 && L2 > 1 ? L2 / 2 : 1;
+    float2 w1[L1 / 2 > 0 ? L1 / 2 : 1], w2[NW2];
 #pragma unroll
     for (int j = 0; j < L1 / 2; ++j) w1[j] = a.tw[j * (L / L1)];       // W_L1^j
+    if constexpr (P == 1) {
 #pragma unroll
-    for (int j = 0; j < L2 / 2; ++j) w2[j] = a.tw[j * (L / L2)];       // W_L2^j
+        for (int j = 0; j < L2 / 2; ++j) w2[j] = a.tw[j * (L / L2)];   // W_L2^j
+    }
     float2 twr[kTwReg && L2 > 1 ? L1 : 1];
     if constexpr (kTwReg && L2 > 1) {
 #pragma unroll
         for (int i = 0; i < L1; ++i) twr[i] = a.tw[(r * i) % L];        // W_L^(r k1)
     }
+    float2 tw2[P > 1 ? L1 : 1];                                         // W_L2^(h m2), h = r % P
+    if constexpr (P > 1) {
+#pragma unroll
+        for (int m = 0; m < L1; ++m) tw2[m] = a.tw[(((r % P) * m) % L2) * (L / L2)];
+    }
     float sc[XP == MWAX_X_INT8 && kTwReg && !STATS ? L1 : 1];
     if constexpr (XP == MWAX_X_INT8 && kTwReg && !STATS) {
 #pragma unroll
-        for (int i = 0; i < L1; ++i) sc[i] = a.inv_s[chan_of<L>(r, i)];
+        for (int i = 0; i < L1; ++i) sc[i] = a.inv_s[chan_of<L, XP>(r, i)];
     }
     float acc[STATS ? L1 : 1];
 #pragma unroll
@@ -319,7 +354,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                 if constexpr (STATS) {
                     acc[i] += X.x * X.x + X.y * X.y;
                 } else {
-                    const int c = chan_of<L>(r, i);
+                    const int c = chan_of<L, XP>(r, i);
                     uint8_t *row = outbuf + c * CP + nl * kRowBytes + row_re_off(pk * FPG, ES);
                     constexpr int IM = row_im_gap(ES);
                     if constexpr (XP == MWAX_X_INT8) {
@@ -380,34 +415,40 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     else w = a.tw[(r * k1) % L];
                     v[k1] = make_float2(v[k1].x * w.x - v[k1].y * w.y, v[k1].x * w.y + v[k1].y * w.x);
                 }
-                // exchange through LDS; column swizzle r ^ (k1 / U) keeps both the
-                // writes (fixed k1) and the reads (fixed r2) free of bank conflicts
-                if constexpr (C::SPLIT_EX) {
-                    // real parts, then imaginary parts, through a float buffer
-                    float *ef = reinterpret_cast<float *>(ex) + gg * EXG;
-                    float2 wv[L1];
+                if constexpr (P > 1) {
+                    // lane r writes its column of the L1 x L2 block (row pitch
+                    // L2 + P keeps the writes and the strided reads below free of
+                    // bank conflicts); lane (k1, h) = (r / P, r % P) then takes
+                    // rows h + P m of column k1: an in-lane 16-point DFT, the
+                    // twiddle W_L2^(h m2), and log2 P radix-2 stages across the P
+                    // lanes, after which lane h holds block q = bitrev_P(h) of
+                    // that column's transform
+                    float2 *eg = ex + gg * EXG;
 #pragma unroll
-                    for (int k1 = 0; k1 < L1; ++k1) ef[k1 * L2 + (r ^ (k1 / U))] = v[k1].x;
+                    for (int k1 = 0; k1 < L1; ++k1) eg[k1 * C::EXR + r] = v[k1];
                     wave_sync();
+                    const int k1 = r / P, h = r % P;
+                    float2 w[L1];
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
+                    for (int m = 0; m < L1; ++m) w[m] = eg[k1 * C::EXR + h + P * m];
+                    dft_regs<L1>(w, w1);
 #pragma unroll
-                        for (int r2 = 0; r2 < L2; ++r2) wv[u * L2 + r2].x = ef[(r * U + u) * L2 + (r2 ^ r)];
-                    wave_sync();
+                    for (int m = 1; m < L1; ++m)
+                        w[m] = make_float2(w[m].x * tw2[m].x - w[m].y * tw2[m].y,
+                                           w[m].x * tw2[m].y + w[m].y * tw2[m].x);
+                    if constexpr (P == 4) {
+                        lane_dif_stage<2, L1>(w, (h & 2) ? -1.0f : 1.0f);
+                        if (h == 3) {       // upper half, second lane: times W_4 = -i
 #pragma unroll
-                    for (int k1 = 0; k1 < L1; ++k1) ef[k1 * L2 + (r ^ (k1 / U))] = v[k1].y;
-                    wave_sync();
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int r2 = 0; r2 < L2; ++r2) wv[u * L2 + r2].y = ef[(r * U + u) * L2 + (r2 ^ r)];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        dft_regs<L2>(wv + u * L2, w2);
-#pragma unroll
-                        for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, wv[u * L2 + k2]);
+                            for (int m = 0; m < L1; ++m) w[m] = make_float2(w[m].y, -w[m].x);
+                        }
                     }
+                    lane_dif_stage<1, L1>(w, (h & 1) ? -1.0f : 1.0f);
+#pragma unroll
+                    for (int m2 = 0; m2 < L1; ++m2) emit(m2, w[m2]);
                 } else {
+                    // exchange through LDS; column swizzle r ^ (k1 / U) keeps both the
+                    // writes (fixed k1) and the reads (fixed r2) free of bank conflicts
                     float2 *eg = ex + gg * EXG;
 #pragma unroll
                     for (int k1 = 0; k1 < L1; ++k1) eg[k1 * L2 + (r ^ (k1 / U))] = v[k1];
@@ -456,7 +497,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             const int rr = t / L1, i = t - rr * L1;
             double sum = 0.0;
             for (int sl = 0; sl < NSLOT; ++sl) sum += (double)red[(sl * L2 + rr) * L1 + i];
-            a.stats[(int64_t)wg * L + chan_of<L>(rr, i)] = sum;
+            a.stats[(int64_t)wg * L + chan_of<L, XP>(rr, i)] = sum;
         }
     }
 }
