@@ -6,10 +6,15 @@ one by one.  Voltages are seeded and made on the device; the oracle sees the
 exact int8 samples the GPU consumed (copied back).
 
 INT8 checks, per sampled (channel, pair), relative to sqrt(V_aa V_bb):
-  * against the oracle's own INT8 chain -- its calibration over all inputs (the
-    rule of mwax_channelise), its requantisation of its FP64 spectra, its
-    integer X-engine -- below 2e-4: the chains differ only where an FP32 and an
-    FP64 spectrum fall on different sides of a rounding boundary;
+  * batch (the instance's codes read back): the int64 sums equal the oracle's
+    integer X-engine on the GPU's own codes, bit for bit; those codes equal the
+    oracle's requantisation of its FP64 spectra except where the FP32 and FP64
+    spectra fall on different sides of a rounding boundary (at most 1e-5 of the
+    codes, by 1; measured 2.3e-6 at L = 1024);
+  * stream (whose integrations span calls, so no block holds all their codes):
+    against the oracle's own INT8 chain -- its calibration over all inputs (the
+    rule of mwax_channelise), its requantisation of its FP64 spectra, its integer
+    X-engine -- below 2e-4;
   * against FP64: below 1.25x the oracle INT8 chain's own error + 2e-4.  That
     error is a property of the encoding, not of the GPU: a bin-centred tone
     repeats its requantisation error in every spectrum, so it does not average
@@ -48,16 +53,20 @@ def pair_cols(sel):
     return [sel[a] * (sel[a] + 1) // 2 + sel[b] for a in range(len(sel)) for b in range(a + 1)]
 
 
-def check_int8(got, cal_rows, rows, sel, L, T, j, label):
+def check_int8(got, cal_rows, rows, sel, L, T, j, label, raw=None, codes=None):
     """got: complex [L][npairs] GPU visibilities of integration j at the sampled
     pairs; cal_rows: int8 [n_in][>= 131072][2] voltages of every input from the
     start of integration j (the calibration window); rows: int8 [k][...][2]
-    voltages of the sampled inputs from the start of the block."""
+    voltages of the sampled inputs from the start of the block.  With raw (int64
+    [L][npairs][2] sums) and codes (int8 [T][L][k][2], the GPU's codes of the
+    sampled inputs over integration j) the codes are checked instead of the
+    chain."""
     ncal = min(T, -(-131072 // L))
     _, s_o, inv_o = oracle.calibrate(oracle.channelise(cal_rows, L, nm=ncal))
     spec = oracle.channelise(rows, L, m0=j * T, nm=T)
     ref = oracle.correlate(spec, T, threads=8)[0]
-    vi = oracle.correlate_i64(oracle.requantise(spec, inv_o), T)[0].astype(np.float64)
+    qo = oracle.requantise(spec, inv_o)
+    vi = oracle.correlate_i64(qo, T)[0].astype(np.float64)
     v8 = (vi[..., 0] + 1j * vi[..., 1]) * (s_o.astype(np.float64) ** 2)[:, None]
     k = len(sel)
     auto = np.stack([ref[:, a * (a + 1) // 2 + a].real for a in range(k)], 1)
@@ -66,7 +75,14 @@ def check_int8(got, cal_rows, rows, sel, L, T, j, label):
     e_gpu = float(np.max(np.abs(got - ref) / scale))
     e_chain = float(np.max(np.abs(v8 - ref) / scale))
     log(f"{label}: vs oracle int8 chain {d_chain:.3g}; vs FP64 {e_gpu:.3g} (oracle int8 chain {e_chain:.3g})")
-    assert d_chain < 2e-4
+    if codes is None:
+        assert d_chain < 2e-4
+    else:
+        assert np.array_equal(raw, oracle.correlate_i64(codes, T)[0])
+        d = codes.astype(np.int32) - qo.astype(np.int32)
+        nd = np.count_nonzero(d)
+        log(f"{label}: {nd} of {d.size} codes differ from the oracle's FP64 requantisation")
+        assert nd <= 1e-5 * d.size and np.abs(d).max() <= 1
     assert e_gpu < 1.25 * e_chain + 2e-4
 
 
@@ -94,15 +110,20 @@ def test_c4_batch_full_shape_sampled():
     sel = [0, 1, 2, 130, 257, 400, 511]
     cols = torch.tensor(pair_cols(sel), device="cuda")
     host = {i: volts[i].cpu().numpy() for i in check}
-    got = {}
+    sel_t = torch.tensor(sel, device="cuda")
+    got, raws, codes = {}, {}, {}
     with Batch(cfgs) as b:
         kc, grid = b.autotune(volts, trials=1)
         log(f"C4 full shape: autotuned kchunk={kc} grid={grid}")
         b.run(volts)
         for i in check:
-            vis = b.plans[i].integrate(4)
-            assert vis.shape[0] == 2, f"instance {i}: {vis.shape[0]} integrations emitted"
-            got[i] = vis.index_select(2, cols).cpu().numpy().astype(np.complex128)
+            p = b.plans[i]
+            codes[i] = p.read_channelised().index_select(2, sel_t).cpu().numpy()   # [m][L][k][2]
+            raw, sc = p.integrate_raw(4)
+            assert raw.shape[0] == 2, f"instance {i}: {raw.shape[0]} integrations emitted"
+            raws[i] = raw.index_select(2, cols).cpu().numpy()
+            s2 = sc.cpu().numpy().astype(np.float64) ** 2
+            got[i] = (raws[i][..., 0] + 1j * raws[i][..., 1]) * s2[:, :, None]
         b.sync()
     del volts
     torch.cuda.empty_cache()
@@ -111,7 +132,8 @@ def test_c4_batch_full_shape_sampled():
         T = int(round(tau * F_S / Lc))
         for j in js:
             check_int8(got[i][j], host[i][:, j * T * Lc:j * T * Lc + 131072], host[i][sel], sel, Lc, T, j,
-                       f"C4 instance {i} (L={Lc}) integration {j}")
+                       f"C4 instance {i} (L={Lc}) integration {j}", raw=raws[i][j],
+                       codes=codes[i][j * T:(j + 1) * T])
 
 
 def test_c5_stream_full_shape_sampled():
