@@ -321,7 +321,7 @@ typedef struct {
     uint64_t block_bytes;       /* n_inputs * block_samples * 2                            */
     int64_t block_ld;           /* samples between input rows of a buffer (block_samples)  */
     void *ingest_stream;        /* hipStream_t to write buffers on before submitting       */
-    void *compute_stream;       /* hipStream_t the plans run on                            */
+    void *compute_stream;       /* hipStream_t ordered after each submitted block (plans run on two lane streams it joins) */
     uint64_t device_bytes;      /* device memory held: pool, plans, output rings           */
 } mwax_stream_info;
 

@@ -4,10 +4,15 @@
 //
 // A pool of device block buffers, sized by an HBM budget, is the admission
 // control: a producer acquires a free buffer, writes a block into it on the
-// ingest stream and submits it for a channel.  The compute stream waits for
-// the ingest, runs that channel's plan over the block and emits its completed
-// integrations into the channel's device output ring.  A buffer returns to the
-// pool when the event recorded after its block's work has completed.  Ready
+// ingest stream and submits it for a channel.  The channel's lane stream waits
+// for the ingest, runs that channel's plan over the block and emits its
+// completed integrations into the channel's device output ring.  Channels
+// alternate between two lane streams, so the launches of neighbouring channels
+// overlap and fill each other's drain tails (a 1 s call at 256 tiles is a pair
+// of ~1 ms launches); the compute stream then waits for the block's lane, so
+// blocks complete, and work a caller enqueues on the compute stream runs, in
+// submission order.  A buffer returns to the pool when the event recorded after
+// its block's work has completed.  Ready
 // times are event timestamps converted to the stream clock through a reference
 // event recorded (and waited for) at creation.
 #include <algorithm>
@@ -24,12 +29,14 @@ using namespace mwax;
 namespace {
 
 constexpr int kMaxChannels = 64;
+constexpr int kLanes = 2;   // per-channel work streams (with ingest and compute: 4 hardware queues)
 
 enum SlotState { kFree = 0, kAcquired = 1, kBusy = 2 };
 
 struct InFlight {
     mwax_block_done rec;
-    hipEvent_t done;
+    hipEvent_t done;    // on the compute stream, after the block's work
+    hipEvent_t join;    // on the block's lane stream (waited for by the compute stream)
 };
 
 }  // namespace
@@ -38,6 +45,7 @@ struct mwax_stream_s {
     mwax_stream_config cfg{};
     int device = 0;
     hipStream_t ingest = nullptr, compute = nullptr;
+    hipStream_t lanes[kLanes] = {};
     std::vector<mwax_plan> plans;
     std::vector<int64_t> blocks_seen;       // per channel
     int n_in = 0, L = 0;
@@ -64,9 +72,14 @@ double now_s(mwax_stream s) {
 
 void free_stream(mwax_stream s) {
     if (!s) return;
+    for (auto l : s->lanes)
+        if (l) (void)hipStreamSynchronize(l);
     if (s->compute) (void)hipStreamSynchronize(s->compute);
     if (s->ingest) (void)hipStreamSynchronize(s->ingest);
-    for (auto &f : s->inflight) (void)hipEventDestroy(f.done);
+    for (auto &f : s->inflight) {
+        (void)hipEventDestroy(f.done);
+        (void)hipEventDestroy(f.join);
+    }
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
     for (auto e : s->ingest_ev) (void)hipEventDestroy(e);
     if (s->ev_ref) (void)hipEventDestroy(s->ev_ref);
@@ -75,6 +88,8 @@ void free_stream(mwax_stream s) {
     for (auto p : s->plans) free_plan(p);
     if (s->ingest) (void)hipStreamDestroy(s->ingest);
     if (s->compute) (void)hipStreamDestroy(s->compute);
+    for (auto l : s->lanes)
+        if (l) (void)hipStreamDestroy(l);
     delete s;
 }
 
@@ -110,6 +125,7 @@ int retire_front(mwax_stream s, bool wait, mwax_block_done *out) {
     if (out) *out = f.rec;
     s->state[f.rec.slot] = kFree;
     s->ev_pool.push_back(f.done);
+    s->ev_pool.push_back(f.join);
     s->inflight.pop_front();
     return 1;
 }
@@ -169,13 +185,14 @@ mwax_status mwax_stream_create(const mwax_stream_config *cfg, mwax_stream *out) 
     s->block_bytes = block_bytes;
     hipError_t e = hipStreamCreateWithFlags(&s->ingest, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l) e = hipStreamCreateWithFlags(&s->lanes[l], hipStreamNonBlocking);
     if (e != hipSuccess) {
         free_stream(s);
         return hip_fail(e, "stream creation");
     }
     for (int k = 0; k < cfg->n_channels; ++k) {
         mwax_plan p = nullptr;
-        st = mwax_plan_create(&cfg->cfg, s->compute, &p);
+        st = mwax_plan_create(&cfg->cfg, s->lanes[k % kLanes], &p);
         if (st != MWAX_OK) {
             std::string m = mwax_last_error();
             free_stream(s);
@@ -300,6 +317,11 @@ mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, dou
                     s->cfg.out_depth);
     hipEvent_t done = stream_event(s);
     if (!done) return fail(MWAX_E_NOMEM, "event creation");
+    hipEvent_t join = stream_event(s);
+    if (!join) {
+        s->ev_pool.push_back(done);
+        return fail(MWAX_E_NOMEM, "event creation");
+    }
     mwax_block_done rec{};
     rec.channel = channel;
     rec.slot = slot;
@@ -308,10 +330,12 @@ mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, dou
     rec.t_arrival_s = t_arrival_s;
     rec.t_submit_s = now_s(s);
 
+    hipStream_t lane = s->lanes[channel % kLanes];
     hipError_t e = hipEventRecord(s->ingest_ev[slot], s->ingest);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->ingest_ev[slot], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(lane, s->ingest_ev[slot], 0);
     if (e != hipSuccess) {
         s->ev_pool.push_back(done);
+        s->ev_pool.push_back(join);
         return hip_fail(e, "ingest ordering");
     }
     const int64_t chunk = s->cfg.cfg.max_samples, ld = s->cfg.block_samples;
@@ -334,17 +358,22 @@ mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, dou
     }
     // The plan calls validated their arguments up front, so a failure here is a
     // device error; the buffer still stays busy until the work enqueued on it ends.
-    e = hipEventRecord(done, s->compute);
+    // The compute stream joins the lane.
+    e = hipEventRecord(join, lane);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, join, 0);
+    if (e == hipSuccess) e = hipEventRecord(done, s->compute);
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(lane);
         (void)hipStreamSynchronize(s->compute);
         s->ev_pool.push_back(done);
+        s->ev_pool.push_back(join);
         s->state[slot] = kFree;
         return hip_fail(e, "completion event");
     }
     rec.n_ints = n_ints;
     s->state[slot] = kBusy;
     s->blocks_seen[channel] += 1;
-    s->inflight.push_back({rec, done});
+    s->inflight.push_back({rec, done, join});
     return st == MWAX_OK ? ok() : st;
 }
 
