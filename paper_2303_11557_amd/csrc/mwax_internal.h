@@ -129,7 +129,8 @@ struct XArgs {
     int32_t tile;           // tile edge (rows)
     void *integ;            // this slot's integrators [L][P][2] (int64 or double)
     int64_t P;
-    int32_t nks;            // chunks of row groups per tile (set by launch_xengine)
+    int32_t nks;            // chunks of row groups per tile (set by launch_xengine;
+                            // 1 on entry: whole segments)
     int32_t kchunk;         // row groups per chunk
     int32_t first;          // the segment starts its integration: a tile's first
                             // non-atomic flush stores instead of adding

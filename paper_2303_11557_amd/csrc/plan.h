@@ -61,6 +61,10 @@ struct mwax_plan_s {
     // (whole-segment INT8/FP16 work of a batch); mwax_correlate clears a slot
     // itself before accumulating into one that was not cleared.
     bool clear_on_emit = true;
+    // X-engine launches run whole segments (no K-chunks with atomic flushes).
+    // Chunks fill the resident slots of a launch running alone; the stream
+    // runtime sets this, because its two lanes fill each other's launch tails.
+    bool whole_segments = false;
 
     bool timing = false;
     struct Ev { hipEvent_t a, b; int fam; };

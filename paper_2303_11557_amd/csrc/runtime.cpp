@@ -205,6 +205,7 @@ XArgs mwax::xengine_args(mwax_plan p, const Segment &s) {
     a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
     a.P = p->P;
     a.first = s.local0 == 0;
+    a.nks = p->whole_segments ? 1 : 0;   // 0: launch_xengine chooses
     return a;
 }
 

@@ -199,6 +199,8 @@ mwax_status mwax_stream_create(const mwax_stream_config *cfg, mwax_stream *out) 
             return fail(st, "channel %d: %s", k, m.c_str());
         }
         p->in_batch = true;
+        p->whole_segments = true;                       // the lanes fill each other's tails
+        p->clear_on_emit = p->xprec == MWAX_X_FP32;     // whole segments overwrite a slot
         s->plans.push_back(p);
         s->device_bytes += d.workspace_bytes;
         void *r = nullptr;

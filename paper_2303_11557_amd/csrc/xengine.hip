@@ -635,9 +635,10 @@ int pick_chunks(int64_t items, int ngrp, int slots) {
 }  // namespace
 
 namespace {
-// Chunks per tile of a single-plan launch (INT8 only) and their size.
+// Chunks per tile of a single-plan launch (INT8 only; a.nks == 1 on entry asks
+// for whole segments) and their size.
 void set_chunks(int xprec, XArgs &a) {
-    a.nks = xprec == MWAX_X_INT8 ? pick_chunks((int64_t)a.ntiles * a.L, a.ngrp, resident_slots()) : 1;
+    if (a.nks != 1) a.nks = xprec == MWAX_X_INT8 ? pick_chunks((int64_t)a.ntiles * a.L, a.ngrp, resident_slots()) : 1;
     a.kchunk = (a.ngrp + a.nks - 1) / a.nks;
     a.nks = (a.ngrp + a.kchunk - 1) / a.kchunk;   // no empty chunk
 }
