@@ -193,11 +193,11 @@ __device__ __forceinline__ uint32_t quant8_bits(float x, float s) {
     return __float_as_uint(fminf(fmaxf(r, kMagic - 127.0f), kMagic + 127.0f));
 }
 
-template <int L>
-__device__ __forceinline__ float2 load_pair_biased(const uint8_t *p) {
-    // one complex int8 sample as (re + 128, im + 128): exact, unsigned conversion
-    const uint32_t w = (uint32_t)(*reinterpret_cast<const uint16_t *>(p)) ^ 0x8080u;
-    return make_float2((float)(w & 0xffu), (float)((w >> 8) & 0xffu));
+// One complex int8 sample, converted exactly (one sign-extending byte convert
+// per component).
+__device__ __forceinline__ float2 load_pair(const uint8_t *p) {
+    const uint32_t w = *reinterpret_cast<const uint16_t *>(p);
+    return make_float2((float)(int8_t)w, (float)(int8_t)(w >> 8));
 }
 
 // The work of workgroup wg of nwg workgroups on the segment described by a.
@@ -248,7 +248,6 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     float acc[STATS ? L1 : 1];
 #pragma unroll
     for (int i = 0; i < (STATS ? L1 : 1); ++i) acc[i] = 0.0f;
-    const float bias = 128.0f * (float)L;      // DC offset of the biased input
 
     // Staging of the raw frames (two-pass split) through registers; with
     // PREFETCH the global loads of the next item are issued before the current
@@ -325,32 +324,28 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     const uint8_t *src = reinterpret_cast<const uint8_t *>(a.volts) +
                                          ((int64_t)(n0 + nl) * a.ld + (src_frame + f) * L) * 2;
                     if constexpr (L == 1) {
-                        v[0] = load_pair_biased<L>(src);
+                        v[0] = load_pair(src);
                     } else {
 #pragma unroll
                         for (int q = 0; q < L / 2; ++q) {
-                            const uint32_t wv = *reinterpret_cast<const uint32_t *>(src + 4 * q) ^ 0x80808080u;
-                            v[2 * q] = make_float2((float)(wv & 0xffu), (float)((wv >> 8) & 0xffu));
-                            v[2 * q + 1] = make_float2((float)((wv >> 16) & 0xffu), (float)(wv >> 24));
+                            const uint32_t wv = *reinterpret_cast<const uint32_t *>(src + 4 * q);
+                            v[2 * q] = make_float2((float)(int8_t)wv, (float)(int8_t)(wv >> 8));
+                            v[2 * q + 1] = make_float2((float)(int8_t)(wv >> 16), (float)(int8_t)(wv >> 24));
                         }
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < L; ++q) v[q] = make_float2(128.0f, 128.0f);
+                    for (int q = 0; q < L; ++q) v[q] = make_float2(0.0f, 0.0f);
                 }
             } else {
                 const uint8_t *fr = stage + (nl * G + f) * SP;
 #pragma unroll
-                for (int n1 = 0; n1 < L1; ++n1) v[n1] = load_pair_biased<L>(fr + 2 * (r + L2 * n1));
+                for (int n1 = 0; n1 < L1; ++n1) v[n1] = load_pair(fr + 2 * (r + L2 * n1));
             }
             dft_regs<L1>(v, w1);
 
             // consume output slot i (FFT bin of this lane) with value X
             auto emit = [&](int i, float2 X) {
-                if (i == 0 && r == 0) {            // bin 0 carries the input bias
-                    X.x -= bias;
-                    X.y -= bias;
-                }
                 if constexpr (STATS) {
                     acc[i] += X.x * X.x + X.y * X.y;
                 } else {
