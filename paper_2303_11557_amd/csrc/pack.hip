@@ -10,18 +10,39 @@
 //             conjugate of the mirrored entry.
 //   raw     : out[c][p] = the exact int64 sums (INT8 integrators).
 // scale: INT8 V_int * s_c * s_c (computed in FP64), FP16 and FP32 V * post.
+//
+// INT8 integrators hold Im V[n1,n2] - sum_m re_n1[m] (the X-engine forms its
+// imaginary operand from one's complements); the autos, whose imaginary parts
+// are zero, therefore hold -sum_m re_n1[m], and every entry of row n1 is
+// corrected exactly by subtracting its auto's imaginary part.  So INT8 slots are
+// cleared by a separate fill after the pack, never while it reads them.
 #include "mwax_internal.h"
 
 namespace mwax {
 namespace {
 
-__device__ __forceinline__ float2 scaled(const PackArgs &a, int64_t idx, int c) {
+__device__ __forceinline__ int64_t tri_row(int64_t t) {
+    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    return i;
+}
+
+// Exact INT8 sums of entry p = n1(n1+1)/2 + n2 of channel c.
+__device__ __forceinline__ longlong2 int_vis(const PackArgs &a, int c, int64_t n1, int64_t p) {
+    const longlong2 *integ = reinterpret_cast<const longlong2 *>(a.integ) + (int64_t)c * a.P;
+    longlong2 v = integ[p];
+    v.y -= integ[n1 * (n1 + 1) / 2 + n1].y;
+    return v;
+}
+
+__device__ __forceinline__ float2 scaled(const PackArgs &a, int64_t p, int64_t n1, int c) {
     if (a.is_int) {
-        const longlong2 v = reinterpret_cast<const longlong2 *>(a.integ)[idx];
+        const longlong2 v = int_vis(a, c, n1, p);
         const double s = (double)a.scales[c];
         return make_float2((float)((double)v.x * s * s), (float)((double)v.y * s * s));
     }
-    const double2 v = reinterpret_cast<const double2 *>(a.integ)[idx];
+    const double2 v = reinterpret_cast<const double2 *>(a.integ)[(int64_t)c * a.P + p];
     return make_float2((float)(v.x * a.post), (float)(v.y * a.post));
 }
 
@@ -30,16 +51,14 @@ __global__ void pack_tri_kernel(PackArgs a) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(t / a.P);
+        const int64_t p = t - (int64_t)c * a.P;
         if (a.order == 2) {
-            longlong2 *src = reinterpret_cast<longlong2 *>(a.integ) + t;
-            reinterpret_cast<longlong2 *>(a.out)[t] = *src;
-            if (a.clear) *src = make_longlong2(0, 0);
+            reinterpret_cast<longlong2 *>(a.out)[t] = int_vis(a, c, tri_row(p), p);
+        } else if (a.is_int) {
+            reinterpret_cast<float2 *>(a.out)[t] = scaled(a, p, tri_row(p), c);
         } else {
-            reinterpret_cast<float2 *>(a.out)[t] = scaled(a, t, c);
-            if (a.clear) {
-                if (a.is_int) reinterpret_cast<longlong2 *>(a.integ)[t] = make_longlong2(0, 0);
-                else reinterpret_cast<double2 *>(a.integ)[t] = make_double2(0.0, 0.0);
-            }
+            reinterpret_cast<float2 *>(a.out)[t] = scaled(a, p, 0, c);
+            if (a.clear) reinterpret_cast<double2 *>(a.integ)[t] = make_double2(0.0, 0.0);
         }
     }
     if (a.scales_out) {
@@ -47,13 +66,6 @@ __global__ void pack_tri_kernel(PackArgs a) {
              c += (int64_t)gridDim.x * blockDim.x)
             a.scales_out[c] = a.scales[c];
     }
-}
-
-__device__ __forceinline__ int64_t tri_row(int64_t t) {
-    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    return i;
 }
 
 // gather pass of the tile-baseline order (integrators cleared afterwards)
@@ -71,9 +83,9 @@ __global__ void pack_tilebl_kernel(PackArgs a) {
         const int64_t r = 2 * ta + (pp >> 1), s = 2 * tb + (pp & 1);
         float2 v;
         if (r >= s) {
-            v = scaled(a, (int64_t)c * a.P + r * (r + 1) / 2 + s, c);
+            v = scaled(a, r * (r + 1) / 2 + s, r, c);
         } else {
-            v = scaled(a, (int64_t)c * a.P + s * (s + 1) / 2 + r, c);
+            v = scaled(a, s * (s + 1) / 2 + r, s, c);
             v.y = -v.y;
         }
         reinterpret_cast<float2 *>(a.out)[t] = v;
@@ -113,7 +125,9 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
         return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
     }
     hipLaunchKernelGGL(pack_tri_kernel, dim3(grid_for((int64_t)a.L * a.P)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.clear || !a.is_int) return e;
+    return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
 }
 
 }  // namespace mwax

@@ -117,12 +117,12 @@ struct MfmaT<MWAX_X_FP16> {
 // The Im operand B2 is formed in registers from the B fragment: its two 8-byte
 // quarters (real parts, imaginary parts of the same frames) are swapped and the
 // imaginary one is flipped -- FP16 by its sign bits, INT8 by its one's
-// complement ~x = -x - 1.  The INT8 form therefore yields Im V[n1,n2] -
-// sum_m re_n1[m]; the row sums sum_m re_n1[m] are accumulated alongside (dot
-// products of the A fragments' real quarter with ones) and added back when the
-// partial sums are flushed, so the result stays exact.  With ~im in [-128, 126]
-// a row group adds at most 127 * 128 * 16 + 127^2 * 16 to a partial, and 65536
-// spectra stay below 2^31.
+// complement ~x = -x - 1.  The INT8 integrators therefore hold Im V[n1,n2] -
+// sum_m re_n1[m], and the autos (whose imaginary parts are zero) hold exactly
+// -sum_m re_n1[m]: the pack step subtracts an entry's auto from it, which makes
+// the result exact without any extra work in this loop.  With ~im in
+// [-128, 126] a row group adds at most 127 * 128 * 16 + 127^2 * 16 to a partial,
+// and 65536 spectra stay below 2^31.
 constexpr int kXG = 2;                      // row groups per stage
 constexpr int kNBuf = 4;                    // stage buffers
 constexpr int kDist = 2;                    // stages copied ahead of the matrix work (< kNBuf)
@@ -197,7 +197,6 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     };
 
     acc_t re[2][2], im[2][2];
-    int sre[2];                                   // INT8: row sums of the re codes (both halves)
     // fragment m of a wave's 64 rows is block 2 * w + m; lane (half, l32) reads
     // half `half` of its row l32
     const int fa_off = wr * 2 * kBlock + half * 512 + l32 * 16;
@@ -226,11 +225,6 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             for (int m = 0; m < 2; ++m) {
                 const uint4 v = fb[sl][m];
                 fb2[m] = make_uint4(v.z ^ kFlip, v.w ^ kFlip, v.x, v.y);
-                if constexpr (INT8) {
-                    const uint4 f = fa[sl][m];
-                    const int t = __builtin_amdgcn_sdot4((int)f.x, 0x01010101, sre[m], false);
-                    sre[m] = __builtin_amdgcn_sdot4((int)f.y, 0x01010101, t, false);
-                }
             }
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
@@ -288,14 +282,12 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         const int s1 = min(nstages, s0 + kChunkStages);
         if constexpr (ACTIVE) {
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
-                sre[mb] = 0;
+            for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
                     re[mb][nb2] = acc_t{};
                     im[mb][nb2] = acc_t{};
                 }
-            }
         }
         // steady state: every stage copied is whole and before the last one
         const int sfull = min(s1, nstages - kDist - 1);
@@ -329,14 +321,6 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) {
                 const int RB = wr * 2 + mb;
-                int rs[16];
-                if constexpr (INT8) {
-                    // row j of the block: lanes j and j + 32 hold the sums of its two halves;
-                    // output row r of this lane is row (r / 4) * 8 + half * 4 + r % 4
-                    const int tot = sre[mb] + __shfl_xor(sre[mb], 32);
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) rs[r] = __shfl(tot, (r >> 2) * 8 + half * 4 + (r & 3));
-                }
 #pragma unroll
                 for (int nb2 = 0; nb2 < 2; ++nb2) {
                     const int CB = wc * 2 + nb2;
@@ -350,10 +334,10 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
                                 unsigned long long *dst =
                                     reinterpret_cast<unsigned long long *>(ibase) + 2 * ((int64_t)c * a.P + p);
                                 atomicAdd(dst, (unsigned long long)(long long)re[mb][nb2][r]);
-                                atomicAdd(dst + 1, (unsigned long long)((long long)im[mb][nb2][r] + rs[r]));
+                                atomicAdd(dst + 1, (unsigned long long)(long long)im[mb][nb2][r]);
                             } else if constexpr (INT8) {
                                 longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
-                                longlong2 v = make_longlong2(re[mb][nb2][r], (long long)im[mb][nb2][r] + rs[r]);
+                                longlong2 v = make_longlong2(re[mb][nb2][r], im[mb][nb2][r]);
                                 if (!store) {
                                     const longlong2 o = *dst;
                                     v.x += o.x;
