@@ -275,6 +275,27 @@ def test_tile_baseline_order():
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+def test_tile_baseline_order_int8():
+    """INT8 integrators hold Im V minus a row term that the pack step removes
+    with the autos (see pack.hip); the tile-baseline view reads entries of both
+    triangles' orientations, so it must equal the oracle's tile-baseline packing
+    of the oracle's integer X-engine on the GPU's codes, to FP32 output rounding."""
+    n_tiles, L, T = 6, 32, 40
+    v = synth.gaussian_volts(12, L * T, seed=5, sources=[synth.Source(3.0, 7)], L=L)
+    s = np.full(L, 0.25, np.float32)
+    with Plan(make_config(n_tiles, L=L, T=T, xprec="int8", max_samples=L * T)) as p:
+        p.set_scales(s)
+        p.channelise(dev_volts(v))
+        q = p.read_channelised().cpu().numpy()
+        p.correlate()
+        got = to_np_vis(p.integrate(1, order="tile_bl"))[0]
+    vi = oracle.correlate_i64(q, T)[0].astype(np.float64)
+    ref = oracle.pack_tilebl((vi[..., 0] + 1j * vi[..., 1]) * 0.0625, n_tiles)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
+    assert np.any(ref.imag != 0)
+
+
 def test_chunking_and_integration_boundaries():
     # integrations of T = 37 spectra, calls of uneven sizes crossing boundaries
     n_tiles, L, T = 5, 16, 37
