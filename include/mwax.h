@@ -63,7 +63,9 @@ typedef enum {
  *         flushed to FP64 integrators; output scaled back by 2^(2e).
  *   INT8: spectra requantised per channel to q = clamp(rne(X * inv_s_c), -127,
  *         127); X-engine on int8 matrix cores with int32 accumulation flushed to
- *         int64 integrators (exact); output V = V_int * s_c^2. */
+ *         integer integrators, exact: int32 pairs when an integration holds at
+ *         most 65536 spectra, int64 pairs otherwise (the raw output is int64
+ *         either way); output V = V_int * s_c^2. */
 typedef enum { MWAX_X_FP32 = 0, MWAX_X_FP16 = 1, MWAX_X_INT8 = 2 } mwax_xprec;
 
 /* Output orders of mwax_integrate:

@@ -347,6 +347,7 @@ void build_x_tables(mwax_batch b, const std::vector<std::vector<Segment>> &segs,
             x.kchunk = (int32_t)(kc ? std::min<int64_t>(kc, s.ngrp) : s.ngrp);
             x.ksplit = (int32_t)ceil_div(s.ngrp, x.kchunk);
             x.first = xa.first;
+            x.i32 = xa.i32;
             const int d = (int)t.xd.size();
             t.xd.push_back(x);
             t.xd_inst.push_back(i);

@@ -14,6 +14,19 @@ namespace mwax {
 // the matrix cores read: one 16-byte half row per lane.
 constexpr int kRowBytes = 32;
 
+// INT8 integrators are int32 pairs when an integration holds at most this many
+// spectra: |Re V| <= 2 * 127^2 * T and |Im V - sum re| <= 2 * 127^2 * T + 127 T
+// stay below 2^31 (2.122e9 at T = 65536); int64 pairs otherwise.
+constexpr int64_t kInt32MaxSpectra = 65536;
+inline int integ_elem_bytes(int xprec, int64_t T) {
+    return xprec == MWAX_X_INT8 && T <= kInt32MaxSpectra ? 8 : 16;
+}
+// Bytes of one integrator slot [L][P] (padded to 256 so every slot is aligned
+// and can be cleared in 16-byte units).
+inline uint64_t integ_slot_bytes(int xprec, int64_t T, int64_t L, int64_t P) {
+    return ((uint64_t)L * P * integ_elem_bytes(xprec, T) + 255) / 256 * 256;
+}
+
 // Layout of one 32-byte row (G frames of one channel and input, elements of es
 // bytes).  INT8 (G = 16) and binary16 (G = 8): bytes 0..7 hold the real parts of
 // frames 0 .. G/2-1, bytes 8..15 their imaginary parts, bytes 16..31 the same for
@@ -134,6 +147,7 @@ struct XArgs {
     int32_t kchunk;         // row groups per chunk
     int32_t first;          // the segment starts its integration: a tile's first
                             // non-atomic flush stores instead of adding
+    int32_t i32;            // INT8 integrators are int32 pairs (else int64)
 };
 // INT8 launches split every tile's row groups into chunks when that fills the
 // device's resident workgroup slots more evenly (chunks flush with exact int64
@@ -164,6 +178,7 @@ struct XDesc {
     int32_t kchunk;         // row groups per chunk
     int32_t ksplit;         // chunks = ceil(ngrp / kchunk)
     int32_t first;          // as XArgs::first
+    int32_t i32;            // as XArgs::i32
 };
 constexpr int kXBatchMaxDesc = 256;
 constexpr int kXBatchMaxTiles = 256;
@@ -195,6 +210,7 @@ struct PackArgs {
     float *scales_out;      // raw mode: copy of s_c, may be NULL
     int32_t order;          // mwax_order; 2 = raw int64
     int32_t clear;          // zero the integrators after reading them
+    int32_t i32;            // INT8 integrators are int32 pairs (else int64)
     int32_t L;
     int32_t n_in;
     int64_t P;

@@ -28,11 +28,18 @@ __device__ __forceinline__ int64_t tri_row(int64_t t) {
     return i;
 }
 
-// Exact INT8 sums of entry p = n1(n1+1)/2 + n2 of channel c.
+// Exact INT8 sums of entry p = n1(n1+1)/2 + n2 of channel c (int32 or int64
+// integrators; int32 ones are within range, see kInt32MaxSpectra).
 __device__ __forceinline__ longlong2 int_vis(const PackArgs &a, int c, int64_t n1, int64_t p) {
+    const int64_t d = n1 * (n1 + 1) / 2 + n1;
+    if (a.i32) {
+        const int2 *integ = reinterpret_cast<const int2 *>(a.integ) + (int64_t)c * a.P;
+        const int2 v = integ[p];
+        return make_longlong2(v.x, (long long)v.y - integ[d].y);
+    }
     const longlong2 *integ = reinterpret_cast<const longlong2 *>(a.integ) + (int64_t)c * a.P;
     longlong2 v = integ[p];
-    v.y -= integ[n1 * (n1 + 1) / 2 + n1].y;
+    v.y -= integ[d].y;
     return v;
 }
 
@@ -115,6 +122,12 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// integrator bytes of the slot, rounded up to whole 16-byte units (slots are
+// padded to 256 bytes)
+static size_t clear_bytes(const PackArgs &a) {
+    return ((size_t)a.L * a.P * (a.i32 ? 8 : 16) + 15) / 16 * 16;
+}
+
 hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
     if (a.order == MWAX_ORDER_TILE_BL) {
         const int64_t nt = a.n_in / 2;
@@ -122,12 +135,12 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(pack_tilebl_kernel, dim3(grid_for(total)), dim3(256), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !a.clear) return e;
-        return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
+        return launch_fill_zero(a.integ, clear_bytes(a), s);
     }
     hipLaunchKernelGGL(pack_tri_kernel, dim3(grid_for((int64_t)a.L * a.P)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.clear || !a.is_int) return e;
-    return launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
+    return launch_fill_zero(a.integ, clear_bytes(a), s);
 }
 
 }  // namespace mwax

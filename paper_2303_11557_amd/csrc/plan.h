@@ -40,6 +40,7 @@ struct mwax_plan_s {
     int64_t NG = 0;
     void *integ = nullptr;
     size_t slot_bytes = 0;
+    bool integ32 = false;           // INT8 integrators are int32 pairs (T <= kInt32MaxSpectra)
     int nslots = 0;
     float *scales = nullptr;        // [nslots][2][L] (s, inv_s)
     float *fixed = nullptr;         // [2][L] user scales

@@ -96,7 +96,7 @@ mwax_status mwax::derive(const mwax_config *cfg, mwax_dims *o) {
     o->cal_spectra = std::min<int64_t>(T, (kCalSamples + L - 1) / L);
     const int64_t NG = (o->max_spectra + o->group - 1) / o->group + segs;
     const uint64_t chan_b = (uint64_t)L * NG * n_in * kRowBytes;
-    const uint64_t integ_b = (uint64_t)o->n_slots * L * o->n_pairs * 16;
+    const uint64_t integ_b = (uint64_t)o->n_slots * integ_slot_bytes(cfg->xprec, T, L, o->n_pairs);
     const uint64_t small_b = (uint64_t)o->n_slots * 2 * L * 4 + 4 * L * 4 + L * 8 + (uint64_t)kStatsMaxWG * L * 8;
     o->workspace_bytes = chan_b + integ_b + small_b;
     o->sample_time_s = 1.0 / cfg->coarse_bw_hz;
@@ -205,6 +205,7 @@ XArgs mwax::xengine_args(mwax_plan p, const Segment &s) {
     a.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
     a.P = p->P;
     a.first = s.local0 == 0;
+    a.i32 = p->integ32;
     a.nks = p->whole_segments ? 1 : 0;   // 0: launch_xengine chooses
     return a;
 }
@@ -290,7 +291,8 @@ mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan
     p->ntiles = nt * (nt + 1) / 2;
     const int64_t segs = (d.max_spectra + p->T - 1) / p->T + 1;
     p->NG = (d.max_spectra + p->G - 1) / p->G + segs;
-    p->slot_bytes = (size_t)p->L * p->P * 16;
+    p->integ32 = integ_elem_bytes(p->xprec, p->T) == 8;
+    p->slot_bytes = (size_t)integ_slot_bytes(p->xprec, p->T, p->L, p->P);
     p->slot_owner.assign(p->nslots, -1);
     p->slot_count.assign(p->nslots, 0);
 
@@ -471,6 +473,7 @@ static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_i
         a.scales_out = d_scales ? d_scales + (size_t)n * p->L : nullptr;
         a.order = order;
         a.clear = p->clear_on_emit;
+        a.i32 = p->integ32;
         a.L = p->L;
         a.n_in = p->n_in;
         a.P = p->P;

@@ -331,19 +331,36 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
                         if (n1 < a.n_in && n2 <= n1) {
                             const int64_t p = (int64_t)n1 * (n1 + 1) / 2 + n2;
                             if constexpr (ATOMIC) {
-                                unsigned long long *dst =
-                                    reinterpret_cast<unsigned long long *>(ibase) + 2 * ((int64_t)c * a.P + p);
-                                atomicAdd(dst, (unsigned long long)(long long)re[mb][nb2][r]);
-                                atomicAdd(dst + 1, (unsigned long long)(long long)im[mb][nb2][r]);
-                            } else if constexpr (INT8) {
-                                longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
-                                longlong2 v = make_longlong2(re[mb][nb2][r], im[mb][nb2][r]);
-                                if (!store) {
-                                    const longlong2 o = *dst;
-                                    v.x += o.x;
-                                    v.y += o.y;
+                                if (a.i32) {
+                                    int *dst = reinterpret_cast<int *>(ibase) + 2 * ((int64_t)c * a.P + p);
+                                    atomicAdd(dst, (int)re[mb][nb2][r]);
+                                    atomicAdd(dst + 1, (int)im[mb][nb2][r]);
+                                } else {
+                                    unsigned long long *dst =
+                                        reinterpret_cast<unsigned long long *>(ibase) + 2 * ((int64_t)c * a.P + p);
+                                    atomicAdd(dst, (unsigned long long)(long long)re[mb][nb2][r]);
+                                    atomicAdd(dst + 1, (unsigned long long)(long long)im[mb][nb2][r]);
                                 }
-                                *dst = v;
+                            } else if constexpr (INT8) {
+                                if (a.i32) {
+                                    int2 *dst = reinterpret_cast<int2 *>(ibase) + (int64_t)c * a.P + p;
+                                    int2 v = make_int2(re[mb][nb2][r], im[mb][nb2][r]);
+                                    if (!store) {
+                                        const int2 o = *dst;
+                                        v.x += o.x;
+                                        v.y += o.y;
+                                    }
+                                    *dst = v;
+                                } else {
+                                    longlong2 *dst = reinterpret_cast<longlong2 *>(ibase) + (int64_t)c * a.P + p;
+                                    longlong2 v = make_longlong2(re[mb][nb2][r], im[mb][nb2][r]);
+                                    if (!store) {
+                                        const longlong2 o = *dst;
+                                        v.x += o.x;
+                                        v.y += o.y;
+                                    }
+                                    *dst = v;
+                                }
                             } else {
                                 double2 *dst = reinterpret_cast<double2 *>(ibase) + (int64_t)c * a.P + p;
                                 double2 v = make_double2((double)re[mb][nb2][r], (double)im[mb][nb2][r]);
@@ -435,6 +452,7 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
             a.integ = xd.integ;
             a.P = xd.P;
             a.first = xd.first;
+            a.i32 = xd.i32;
             int I, J;
             tile_ij(t, I, J);
             const int rowA0 = I * kTile, rowB0 = J * kTile;

@@ -91,7 +91,8 @@ def test_printed_arithmetic():
 
 
 @pytest.mark.parametrize("L,T,prec,G", [(1, 5, "fp32", 4), (128, 1000, "int8", 16),
-                                         (1024, 625, "fp16", 8), (32, 20000, "int8", 16)])
+                                         (1024, 625, "fp16", 8), (32, 20000, "int8", 16),
+                                         (16, 80000, "int8", 16)])
 def test_derived_dimensions(L, T, prec, G):
     d = mwax.derive(cfg(n_tiles=7, L=L, T=T, xprec=prec, max_samples=L * T * 3))
     assert d.fft_len == L and d.spectra_per_int == T and d.group == G
@@ -101,7 +102,10 @@ def test_derived_dimensions(L, T, prec, G):
     assert d.n_slots >= 3 + 2
     assert d.cal_spectra == min(T, -(-131072 // L))
     assert d.fine_chan_hz == pytest.approx(1.28e6 / L)
-    assert d.workspace_bytes > d.n_slots * L * d.n_pairs * 16
+    # INT8 integrators are int32 pairs up to 65,536 spectra per integration
+    elem = 8 if prec == "int8" and T <= 65536 else 16
+    assert d.workspace_bytes > d.n_slots * L * d.n_pairs * elem
+    assert d.workspace_bytes < d.n_slots * L * d.n_pairs * elem + 3 * T * L * 14 * 32 + (1 << 24)
 
 
 @pytest.mark.parametrize("bad", [
