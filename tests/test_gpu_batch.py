@@ -278,3 +278,30 @@ def test_batch_slots_emitted_without_clearing_are_cleared_before_atomic_use():
             b.sync()
         log(f"{mode}: {ncalls} integrations, {nslots} slots")
         assert_same([got], [ref], f"batch ({mode}) vs single")
+
+
+def test_int32_integrators_at_their_bound():
+    """Integrations of 65,536 spectra use int32 integrators; with every sample
+    at +-127 the autos reach 2 * 127^2 * 65536 = 2.114e9 (just below 2^31).
+    The single-plan path (which splits the segment into atomically added
+    chunks) and the batch path (whole segments, first flush stores) must both
+    equal the oracle's int64 sums bit for bit."""
+    n_tiles, L, M = 2, 1, 65536
+    q = np.full((M, L, 4, 2), 127, np.int8)
+    q[:, :, 1, 1] = -127
+    q[1::2, :, 3, 0] = -127
+    volts = torch.from_numpy(np.ascontiguousarray(q[:, 0].transpose(1, 0, 2))).cuda()   # [n][M][2]
+    cfg = make_config(n_tiles, L=L, T=M, xprec="int8", max_samples=L * M)
+    ref = oracle.correlate_i64(q, M)
+    assert np.abs(ref).max() == 2 * 127 ** 2 * M
+    with Plan(cfg) as p:
+        p.set_scales(np.ones(L, np.float32))
+        p.channelise(volts)
+        p.correlate()
+        raw, _ = p.integrate_raw(1)
+        assert np.array_equal(raw.cpu().numpy(), ref)
+    with Batch([cfg]) as b:
+        b.plans[0].set_scales(np.ones(L, np.float32))
+        b.run([volts])
+        raw, _ = b.plans[0].integrate_raw(1)
+        assert np.array_equal(raw.cpu().numpy(), ref)
