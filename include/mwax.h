@@ -177,9 +177,10 @@ mwax_status mwax_correlate(mwax_plan p);
 
 /* Emit up to max_ints completed integrations, oldest first, into d_vis
  * (complex64 in the given mwax_order; CHAN_TRI needs max_ints * L * P values,
- * TILE_BL max_ints * n_baselines * L * 4), then clear their integrators.
- * *n_emitted receives the count (0 if none is complete).  Integrations still
- * in progress are kept. */
+ * TILE_BL max_ints * n_baselines * L * 4) and free their device slots (the
+ * integrators are cleared, except in plans of a batch or stream whose next
+ * X-engine work overwrites a slot anyway).  *n_emitted receives the count (0
+ * if none is complete).  Integrations still in progress are kept. */
 mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *n_emitted,
                            int32_t order);
 
@@ -299,9 +300,11 @@ mwax_status mwax_batch_sync(mwax_batch b);
  * (mwax_stream_acquire) hands out a free buffer, or waits, or refuses when the
  * budget is exhausted.  Blocks are written into their buffer on the stream's
  * ingest stream (a copy from pinned host memory, mwax_stream_copy_in, or any
- * producer kernel), then submitted; the compute stream waits for the ingest,
- * runs the channel's plan over the block in calls of cfg.max_samples samples,
- * and emits every completed integration into the channel's device output ring.
+ * producer kernel), then submitted; the channel's lane stream (one of two,
+ * channel mod 2) waits for the ingest, runs the channel's plan over the block
+ * in calls of cfg.max_samples samples, and emits every completed integration
+ * into the channel's device output ring; the compute stream then waits for
+ * that lane, so blocks complete in submission order.
  * Block latency = ready time - arrival time, with the ready time taken from a
  * HIP event timestamp on the stream clock.
  * ------------------------------------------------------------------------ */
