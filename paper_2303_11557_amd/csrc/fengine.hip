@@ -62,21 +62,48 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// b * W_N^e with w[j] = W_N^j held in registers; e = 0 and e = N/4 are exact
-// (1 and -i) and need no multiply.
+// cos(2 pi e / N) and tan(2 pi e / N) for e < N/2 (N <= 32), rounded to FP32
+// from their FP64 values; the tangent at e = N/4 is unused (that twiddle is -i).
 template <int N>
-__device__ __forceinline__ float2 tw_mul(float2 b, int e, const float2 *w) {
-    if (e == 0) return b;
-    if (4 * e == N) return make_float2(b.y, -b.x);
-    const float2 t = w[e];
-    return make_float2(b.x * t.x - b.y * t.y, b.x * t.y + b.y * t.x);
-}
+struct TwConst;
+template <>
+struct TwConst<2> {
+    static constexpr float c[1] = {1.0f}, t[1] = {0.0f};
+};
+template <>
+struct TwConst<4> {
+    static constexpr float c[2] = {1.0f, 0.0f}, t[2] = {0.0f, 0.0f};
+};
+template <>
+struct TwConst<8> {
+    static constexpr float c[4] = {1.0f, 0.70710677f, 0.0f, -0.70710677f};
+    static constexpr float t[4] = {0.0f, 1.0f, 0.0f, -1.0f};
+};
+template <>
+struct TwConst<16> {
+    static constexpr float c[8] = {1.0f, 0.92387950f, 0.70710677f, 0.38268343f,
+                                   0.0f, -0.38268343f, -0.70710677f, -0.92387950f};
+    static constexpr float t[8] = {0.0f, 0.41421357f, 1.0f, 2.4142137f, 0.0f, -2.4142137f, -1.0f, -0.41421357f};
+};
+template <>
+struct TwConst<32> {
+    static constexpr float c[16] = {1.0f, 0.98078525f, 0.92387950f, 0.83146960f, 0.70710677f, 0.55557024f,
+                                    0.38268343f, 0.19509032f, 0.0f, -0.19509032f, -0.38268343f, -0.55557024f,
+                                    -0.70710677f, -0.83146960f, -0.92387950f, -0.98078525f};
+    static constexpr float t[16] = {0.0f, 0.19891237f, 0.41421357f, 0.66817862f, 1.0f, 1.4966058f,
+                                    2.4142137f, 5.0273395f, 0.0f, -5.0273395f, -2.4142137f, -1.4966058f,
+                                    -1.0f, -0.66817862f, -0.41421357f, -0.19891237f};
+};
 
 // In-register radix-2 decimation-in-time DFT of N points, natural order in and
-// out; w[j] = W_N^j for j < N/2.
+// out.  A butterfly a +- W b with W = W_N^e = cos(t) - i sin(t), t = 2 pi e/N:
+// e = 0 and e = N/4 (W = -i) are exact; otherwise W b = cos(t) (b_x + b_y tan(t),
+// b_y - b_x tan(t)), so the pair costs six FMAs (two for the bracket, one per
+// output component) instead of a complex multiply and four additions.
 template <int N>
-__device__ __forceinline__ void dft_regs(float2 *v, const float2 *w) {
+__device__ __forceinline__ void dft_regs(float2 *v) {
     if constexpr (N > 1) {
+        using TC = TwConst<N>;
         float2 t[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) t[i] = v[bitrev<N>(i)];
@@ -87,10 +114,20 @@ __device__ __forceinline__ void dft_regs(float2 *v, const float2 *w) {
             for (int base = 0; base < N; base += 2 * h) {
 #pragma unroll
                 for (int j = 0; j < h; ++j) {
-                    const float2 b = tw_mul<N>(t[base + j + h], j * (N / (2 * h)), w);
-                    const float2 a = t[base + j];
-                    t[base + j] = make_float2(a.x + b.x, a.y + b.y);
-                    t[base + j + h] = make_float2(a.x - b.x, a.y - b.y);
+                    const int e = j * (N / (2 * h));
+                    const float2 a = t[base + j], b = t[base + j + h];
+                    if (e == 0) {
+                        t[base + j] = make_float2(a.x + b.x, a.y + b.y);
+                        t[base + j + h] = make_float2(a.x - b.x, a.y - b.y);
+                    } else if (4 * e == N) {               // W b = (b_y, -b_x)
+                        t[base + j] = make_float2(a.x + b.y, a.y - b.x);
+                        t[base + j + h] = make_float2(a.x - b.y, a.y + b.x);
+                    } else {
+                        const float c = TC::c[e], tn = TC::t[e];
+                        const float u = fmaf(b.y, tn, b.x), w = fmaf(-b.x, tn, b.y);
+                        t[base + j] = make_float2(fmaf(c, u, a.x), fmaf(c, w, a.y));
+                        t[base + j + h] = make_float2(fmaf(-c, u, a.x), fmaf(-c, w, a.y));
+                    }
                 }
             }
         }
@@ -222,14 +259,6 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     // two-pass split) holds FFT bin k = (r U + u) + L1 k2, channel (k + L/2) mod L.
     constexpr bool kTwReg = L1 <= 16;
     constexpr int P = C::P;
-    constexpr int NW2 = P == 1 && L2 > 1 ? L2 / 2 : 1;
-    float2 w1[L1 / 2 > 0 ? L1 / 2 : 1], w2[NW2];
-#pragma unroll
-    for (int j = 0; j < L1 / 2; ++j) w1[j] = a.tw[j * (L / L1)];       // W_L1^j
-    if constexpr (P == 1) {
-#pragma unroll
-        for (int j = 0; j < L2 / 2; ++j) w2[j] = a.tw[j * (L / L2)];   // W_L2^j
-    }
     float2 twr[kTwReg && L2 > 1 ? L1 : 1];
     if constexpr (kTwReg && L2 > 1) {
 #pragma unroll
@@ -342,7 +371,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 #pragma unroll
                 for (int n1 = 0; n1 < L1; ++n1) v[n1] = load_pair(fr + 2 * (r + L2 * n1));
             }
-            dft_regs<L1>(v, w1);
+            dft_regs<L1>(v);
 
             // consume output slot i (FFT bin of this lane) with value X
             auto emit = [&](int i, float2 X) {
@@ -426,7 +455,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     float2 w[L1];
 #pragma unroll
                     for (int m = 0; m < L1; ++m) w[m] = eg[k1 * C::EXR + h + P * m];
-                    dft_regs<L1>(w, w1);
+                    dft_regs<L1>(w);
 #pragma unroll
                     for (int m = 1; m < L1; ++m)
                         w[m] = make_float2(w[m].x * tw2[m].x - w[m].y * tw2[m].y,
@@ -454,7 +483,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                         float2 w[L2];
 #pragma unroll
                         for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[k1 * L2 + (r2 ^ r)];
-                        dft_regs<L2>(w, w2);
+                        dft_regs<L2>(w);
 #pragma unroll
                         for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2]);
                     }
