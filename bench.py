@@ -32,7 +32,7 @@ PEAK = {  # MI355X published dense peaks
     "fp32_vector_tflops": 157.3,
 }
 N_TILES, L, SECONDS, F_S = 256, 128, 8.0, 1.28e6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_channel_256tiles_8s.json")
 
 
 def measured_traffic(key):
@@ -51,12 +51,12 @@ def measured_traffic(key):
 # Batch workload: 24 coarse channels as uneven instances (tile counts, FFT
 # lengths, integration times cycled), each with 8 s of sigma = 8 voltages and
 # one seeded point source; run as one batch in 1 s calls.
-C4_TILES, C4_L, C4_TAU = (64, 128, 256), (32, 128, 1024), (0.5, 2.0, 8.0)
-C4_CHUNK_S = 1.0
+BATCH_TILES, BATCH_L, BATCH_TAU = (64, 128, 256), (32, 128, 1024), (0.5, 2.0, 8.0)
+BATCH_CALL_S = 1.0
 
 
-def c4_instances():
-    return [(C4_TILES[i % 3], C4_L[(i // 3) % 3], C4_TAU[(i // 9) % 3]) for i in range(24)]
+def batch_instances():
+    return [(BATCH_TILES[i % 3], BATCH_L[(i // 3) % 3], BATCH_TAU[(i // 9) % 3]) for i in range(24)]
 
 
 def cpu_baseline(volts, L, seconds, what):
@@ -115,12 +115,12 @@ def copy_bandwidth():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
-                    help="c3: one coarse channel, 256 tiles, 8 s (the headline metric); "
-                         "c4: 24 uneven instances as one batch; c5: 24 channels streamed in 8 s blocks")
-    ap.add_argument("--c5-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
-    ap.add_argument("--c5-paced-rounds", type=int, default=4, help="8 s blocks per channel, real-time paced")
-    ap.add_argument("--c5-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
+    ap.add_argument("--workload", default="channel", choices=["channel", "batch", "stream"],
+                    help="channel: one coarse channel, 256 tiles, 8 s (the headline metric); "
+                         "batch: 24 uneven instances as one batch; stream: 24 channels streamed in 8 s blocks")
+    ap.add_argument("--stream-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
+    ap.add_argument("--stream-paced-rounds", type=int, default=4, help="8 s blocks per channel, real-time paced")
+    ap.add_argument("--stream-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--xprec", default="int8", choices=["int8", "fp16", "fp32"])
@@ -134,7 +134,7 @@ def parse():
     return ap.parse_args()
 
 
-def main_c4(args):
+def main_batch(args):
     import torch
 
     import synth
@@ -144,9 +144,9 @@ def main_c4(args):
     torch.cuda.set_device(0)
     mwax.lib()
     S = int(SECONDS * F_S)
-    chunk = int(C4_CHUNK_S * F_S)
+    chunk = int(BATCH_CALL_S * F_S)
     ncalls = S // chunk
-    inst = c4_instances()
+    inst = batch_instances()
     cfgs = [make_config(t, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=chunk) for (t, Lc, tau) in inst]
     dims = [mwax.derive(c) for c in cfgs]
     cmac_per_step = sum(d.n_pairs * S for d in dims)
@@ -209,7 +209,7 @@ def main_c4(args):
               "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(f_gbs / PEAK["hbm_gbs"], 4),
               "traffic": None, "ms_per_step": round(f_ms, 3), "launches": f_n, "bytes_per_step": f_bytes}
     dominant, other = (roof_x, roof_f) if x_ms >= f_ms else (roof_f, roof_x)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(volts[2], C4_L[0], args.cpu_seconds,
+    cpu = None if args.no_cpu_baseline else cpu_baseline(volts[2], BATCH_L[0], args.cpu_seconds,
                                                          "instance 2 (256 tiles, 32-pt FFT)")
     line = {
         "metric": "X-engine CMAC/s & real-time factor, 24 uneven instances in one batch",
@@ -233,7 +233,7 @@ def main_c4(args):
     print(json.dumps(line), flush=True)
 
 
-def main_c5(args):
+def main_stream(args):
     """Streaming: 24 coarse channels x 256 tiles, continuous 8 s blocks, 2 s
     integrations on the device, int8 X-engine, admission by HBM budget.
     (i) blocks resident in the pool (made once by the device generator): the
@@ -256,7 +256,7 @@ def main_c5(args):
     cfg = make_config(n_tiles, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=call)
     d = mwax.derive(cfg)
     n_in, P = d.n_inputs, d.n_pairs
-    budget = int(args.c5_budget_gb * 1e9)
+    budget = int(args.stream_budget_gb * 1e9)
     pad = 1 << 16
     out = {}
     with Stream(cfg, n_ch, block, budget, out_depth=6) as s:
@@ -300,7 +300,7 @@ def main_c5(args):
                     "integrations": int(sum(r["n_ints"] for r in recs))}
 
         out["warmup"] = run(1, "i", False)
-        out["device_resident"] = run(args.c5_rounds, "i", False)
+        out["device_resident"] = run(args.stream_rounds, "i", False)
         # (ii) pinned host pool: one block plus a margin, filled from the device generator
         host = torch.empty((n_in, block + pad, 2), dtype=torch.int8, pin_memory=True)
         gen = torch.empty((n_in, block + pad, 2), dtype=torch.int8, device="cuda")
@@ -308,15 +308,15 @@ def main_c5(args):
         host.copy_(gen)
         del gen
         torch.cuda.empty_cache()
-        out["host_link"] = run(max(1, args.c5_paced_rounds), "ii", False, host)
-        out["paced_host_link"] = run(args.c5_paced_rounds, "ii", True, host)
+        out["host_link"] = run(max(1, args.stream_paced_rounds), "ii", False, host)
+        out["paced_host_link"] = run(args.stream_paced_rounds, "ii", True, host)
         info = s.info
 
     dr = out["device_resident"]
     line = {
         "metric": "real-time factor & block latency, 24 coarse channels x 256 tiles streamed in 8 s blocks",
-        "value": dr["cmac_per_s"], "unit": "CMAC/s", "n_gpus": 1, "steps": args.c5_rounds, "warmup": 1,
-        "ms_per_step": round(dr["wall_s"] * 1e3 / args.c5_rounds, 3), "higher_is_better": True,
+        "value": dr["cmac_per_s"], "unit": "CMAC/s", "n_gpus": 1, "steps": args.stream_rounds, "warmup": 1,
+        "ms_per_step": round(dr["wall_s"] * 1e3 / args.stream_rounds, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.xprec, "data": "synthetic",
         "config": {"workload": "24 channels x 256 tiles x 2 pols, continuous 8 s blocks of complex int8 "
                                "sigma=8 voltages + 1 source, 128-pt FFT, 2 s integrations on device, "
@@ -334,14 +334,14 @@ def main_c5(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(coarse channels shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(coarse channels would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "c4":
-        return main_c4(args)
-    if args.workload == "c5":
-        return main_c5(args)
+    if args.workload == "batch":
+        return main_batch(args)
+    if args.workload == "stream":
+        return main_stream(args)
 
     import torch
 

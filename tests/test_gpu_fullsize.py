@@ -86,16 +86,16 @@ def check_int8(got, cal_rows, rows, sel, L, T, j, label, raw=None, codes=None):
     assert e_gpu < 1.25 * e_chain + 2e-4
 
 
-def c4_instances():
+def batch_instances():
     tiles, lens, taus = (64, 128, 256), (32, 128, 1024), (0.5, 2.0, 8.0)
     return [(tiles[i % 3], lens[(i // 3) % 3], taus[(i // 9) % 3]) for i in range(24)]
 
 
-def test_c4_batch_full_shape_sampled():
+def test_batch_full_shape_sampled():
     """The 24 uneven instances of the batch workload, one 1 s call, autotuned,
     graph replay; the two 0.5 s integrations of three 256-tile instances
     (L = 32, 128, 1024) checked on sampled inputs."""
-    inst = c4_instances()
+    inst = batch_instances()
     chunk = int(F_S)
     cfgs = [make_config(t, L=Lc, int_time_s=tau, xprec="int8", max_samples=chunk) for t, Lc, tau in inst]
     volts = []
@@ -105,7 +105,7 @@ def test_c4_batch_full_shape_sampled():
                            sources=[synth.Source(3.0, (7 * i) % Lc - Lc // 2)], L=Lc)
         volts.append(v)
     torch.cuda.synchronize()
-    log("C4 full shape: voltages made")
+    log("batch full shape: voltages made")
     check = {2: [1], 5: [1], 8: [0, 1]}     # 256 tiles, tau = 0.5 s, L = 32 / 128 / 1024
     sel = [0, 1, 2, 130, 257, 400, 511]
     cols = torch.tensor(pair_cols(sel), device="cuda")
@@ -114,7 +114,7 @@ def test_c4_batch_full_shape_sampled():
     got, raws, codes = {}, {}, {}
     with Batch(cfgs) as b:
         kc, grid = b.autotune(volts, trials=1)
-        log(f"C4 full shape: autotuned kchunk={kc} grid={grid}")
+        log(f"batch full shape: autotuned kchunk={kc} grid={grid}")
         b.run(volts)
         for i in check:
             p = b.plans[i]
@@ -132,11 +132,11 @@ def test_c4_batch_full_shape_sampled():
         T = int(round(tau * F_S / Lc))
         for j in js:
             check_int8(got[i][j], host[i][:, j * T * Lc:j * T * Lc + 131072], host[i][sel], sel, Lc, T, j,
-                       f"C4 instance {i} (L={Lc}) integration {j}", raw=raws[i][j],
+                       f"batch instance {i} (L={Lc}) integration {j}", raw=raws[i][j],
                        codes=codes[i][j * T:(j + 1) * T])
 
 
-def test_c5_stream_full_shape_sampled():
+def test_stream_full_shape_sampled():
     """Two channels of the streaming workload (256 tiles, 8 s blocks, 1 s calls,
     2 s integrations) through the device block pool; channel 0's second block
     checked on sampled inputs (its integrations 4 .. 7)."""
@@ -161,7 +161,7 @@ def test_c5_stream_full_shape_sampled():
         recs = []
         while len(recs) < 3:
             recs += s.poll(-1)
-        log(f"C5 full shape: blocks done, latencies {[round(r['t_ready_s'] - r['t_arrival_s'], 3) for r in recs]}")
+        log(f"stream full shape: blocks done, latencies {[round(r['t_ready_s'] - r['t_arrival_s'], 3) for r in recs]}")
         assert [r["n_ints"] for r in recs] == [4, 4, 4]
         got = {}
         for j in (4, 7):
@@ -171,4 +171,4 @@ def test_c5_stream_full_shape_sampled():
     for j, g in got.items():
         jl = j - 4                     # integration within the second block
         check_int8(g, host[:, jl * T * L:jl * T * L + 131072], host[sel], sel, L, T, jl,
-                   f"C5 channel 0 integration {j}")
+                   f"stream channel 0 integration {j}")

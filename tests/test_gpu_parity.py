@@ -250,14 +250,14 @@ def test_exact_integer_lengths_fp32_and_int8(L):
     assert np.array_equal(raw.cpu().numpy(), oracle.correlate_i64(q.astype(np.int8), T))
 
 
-def test_c1_plain_fp32_full():
-    """16 tiles x 2 pols, 128,000 samples, L = 128, one integration (config 1)."""
+def test_16_tiles_plain_fp32_full():
+    """16 tiles x 2 pols, 128,000 samples, L = 128, one integration."""
     n_tiles, L, T = 16, 128, 1000
     v = synth.gaussian_volts(32, L * T, sigma=8.0, seed=synth.MWAX_SEED)
     ref = oracle.fx_correlate(v, L, T, threads=8)
     got = to_np_vis(run_fx(v, n_tiles, L, T, "fp32"))
     err = rel_frob(got, ref)
-    log(f"C1 fp32 max per-channel rel-Frobenius {err.max():.3g}")
+    log(f"16 tiles fp32 max per-channel rel-Frobenius {err.max():.3g}")
     assert got.shape == (1, L, 32 * 33 // 2)
     assert err.max() <= 1e-5
     # autos real (imaginary part at FP32 rounding level) and positive
@@ -433,8 +433,8 @@ def sampled_check(vis, volts_dev, inputs, L, T, j, tol_fn):
     return worst
 
 
-def test_c2_plain_fp32_sampled():
-    """128 tiles, 1.28 M samples (1 s), one point source, 0.5 s integrations (config 2)."""
+def test_128_tiles_plain_fp32_sampled():
+    """128 tiles, 1.28 M samples (1 s), one point source, 0.5 s integrations."""
     n_tiles, L, T, S = 128, 128, 5000, 1_280_000
     n = 2 * n_tiles
     d = torch.empty((n, S, 2), dtype=torch.int8, device="cuda")
@@ -449,7 +449,7 @@ def test_c2_plain_fp32_sampled():
     inputs = [0, 1, 2, 77, 128, 200, 254, 255]
     for j in range(2):
         w = sampled_check(to_np_vis(vis[j]), d, inputs, L, T, j, 1e-5)
-        log(f"C2 fp32 integration {j}: worst sampled error {w:.3g} (of sqrt(auto1 auto2))")
+        log(f"128 tiles fp32 integration {j}: worst sampled error {w:.3g} (of sqrt(auto1 auto2))")
     # closed-form phase of the source in channel c0 on the sampled pairs
     taus = synth.source_delays(n, seed)
     nu = synth.NU_C + 17 * synth.F_S / L
@@ -465,12 +465,12 @@ def test_c2_plain_fp32_sampled():
 
 
 @pytest.mark.parametrize("prec,tol", [("int8", 2e-3), ("fp16", 5e-4), ("fp32", 1e-5)])
-def test_c3_precision_full_size_sampled(prec, tol):
-    """256 tiles, 8 s (10.24 M samples), three sources, one 8 s integration (config 3)."""
+def test_channel_precision_full_size_sampled(prec, tol):
+    """256 tiles, 8 s (10.24 M samples), three sources, one 8 s integration."""
     n_tiles, L, S = 256, 128, 10_240_000
     T = S // L
     n = 2 * n_tiles
-    log(f"C3 {prec}: generating 10.5 GB of voltages")
+    log(f"256 tiles {prec}: generating 10.5 GB of voltages")
     d = torch.empty((n, S, 2), dtype=torch.int8, device="cuda")
     srcs = [synth.Source(2.0, -37), synth.Source(3.0, 5), synth.Source(4.0, 41)]
     synth.device_volts(d, seed=synth.MWAX_SEED + 2, sources=srcs, L=L)
@@ -479,7 +479,7 @@ def test_c3_precision_full_size_sampled(prec, tol):
         p.correlate()
         vis = p.integrate(1)
         torch.cuda.synchronize()
-    log(f"C3 {prec}: correlated")
+    log(f"256 tiles {prec}: correlated")
     assert vis.shape == (1, L, n * (n + 1) // 2)
     v0 = vis[0]
     autos_idx = torch.tensor([k * (k + 1) // 2 + k for k in range(n)], device="cuda")
@@ -489,6 +489,6 @@ def test_c3_precision_full_size_sampled(prec, tol):
         assert bool(torch.all(autos.imag == 0))
     inputs = [0, 1, 2, 3, 130, 257, 400, 510, 511]
     w = sampled_check(to_np_vis(v0), d, inputs, L, T, 0, tol)
-    log(f"C3 {prec}: worst sampled error {w:.3g} (bound {tol})")
+    log(f"256 tiles {prec}: worst sampled error {w:.3g} (bound {tol})")
     del d, vis
     torch.cuda.empty_cache()
