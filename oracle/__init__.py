@@ -11,6 +11,8 @@ module only marshals numpy arrays.  Conventions (Morrison et al. 2023):
   samples, channels fftshifted so DC sits at c = L/2 (Sec. 2.6).
 * X step (Sec. 2.5.2): V_j[c][n1,n2] = sum_{m in j} X_n1[m,c] conj(X_n2[m,c])
   for n1 >= n2, packed at n1 (n1+1)/2 + n2 (Sec. 2.7).
+* Weights (Sec. 4.1): fraction of an integration's 50 ms sub-blocks populated
+  in both inputs of a pair; optional normalisation V / w.
 """
 from __future__ import annotations
 
@@ -66,9 +68,12 @@ def _load():
                                       _c_f64p, _c_f32p, _c_f32p]
         lib.orc_round_fp16.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_double, _c_f64p]
         lib.orc_pack_tilebl.argtypes = [_c_f64p, ctypes.c_int, ctypes.c_int, _c_f64p]
+        lib.orc_vis_weights.argtypes = [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _c_f64p]
+        lib.orc_apply_weights.argtypes = [_c_f64p, _c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         for f in ("orc_dft", "orc_fft", "orc_channelise", "orc_correlate", "orc_correlate_full",
                   "orc_correlate_i64", "orc_requantise", "orc_calibrate", "orc_round_fp16",
-                  "orc_pack_tilebl"):
+                  "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -227,3 +232,30 @@ def fx_correlate(volts: np.ndarray, L: int, T: int, threads: int = 1) -> np.ndar
     """Whole FP64 chain: voltages [n][S][2] -> packed visibilities [S//L//T][L][P]."""
     spec = channelise(volts, L)
     return correlate(spec, T, threads)
+
+
+def vis_weights(flags: np.ndarray, subs_per_int: int) -> np.ndarray:
+    """Occupancy weights (Sec. 4.1): flags [n][n_ints * subs] (nonzero = zeroed
+    sub-block) -> [n_ints][P] fraction of sub-blocks populated in both inputs."""
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    n, nsub = f.shape
+    if subs_per_int < 1 or nsub % subs_per_int:
+        raise ValueError("flags must hold a whole number of integrations")
+    n_ints = nsub // subs_per_int
+    w = np.empty((n_ints, n_pairs(n)), np.float64)
+    _check(_load().orc_vis_weights(f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n,
+                                   int(subs_per_int), n_ints, _ptr(w, _c_f64p)), "vis_weights")
+    return w
+
+
+def apply_weights(vis, w) -> np.ndarray:
+    """Normalised visibilities (Sec. 4.1): [n_ints][L][P] / w [n_ints][P] where w > 0."""
+    vp = _as_pairs(np.asarray(vis, dtype=np.complex128)).copy()
+    n_ints, L, P = vp.shape[:3]
+    wa = np.ascontiguousarray(w, dtype=np.float64)
+    if wa.shape != (n_ints, P):
+        raise ValueError("weights must be [n_ints][P]")
+    n = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    _check(_load().orc_apply_weights(_ptr(vp, _c_f64p), _ptr(wa, _c_f64p), n, L, n_ints),
+           "apply_weights")
+    return _to_complex(vp)

@@ -22,6 +22,8 @@
  *              V_j[c][n1,n2] = sum_{m in j} X_n1[m,c] conj(X_n2[m,c])
  *   Output   (Sec. 2.7): lower triangle packed row-major,
  *              index(n1,n2) = n1 (n1+1) / 2 + n2.
+ *   Weights  (Sec. 4.1): per pair and integration, the fraction of 50 ms
+ *            sub-blocks populated in both inputs; optional V / w.
  *
  * Encodings the paper does not have (it computes in FP32 throughout,
  * Sec. 2.5.1 and 3.3) but the precision study needs, written out as rules:
@@ -405,5 +407,48 @@ int orc_pack_tilebl(const double *vis_in, int L, int n_tiles, double *vis_out) {
                         o[0] = re; o[1] = im;
                     }
         }
+    return ORC_OK;
+}
+
+/* -------------------------------------------------------------------------
+ * Visibility weights (Sec. 4.1; the capture stage's zeroing flags, Sec. 2.4;
+ * one weight per baseline/polarisation for all fine channels, Sec. 2.7).
+ * flags: [n][n_ints * subs] bytes, nonzero = that input's 50 ms sub-block was
+ * zeroed.  The weight of pair (n1, n2) in integration j is the fraction of
+ * j's sub-blocks in which neither input was zeroed.  w: [n_ints][P].
+ * ------------------------------------------------------------------------- */
+int orc_vis_weights(const uint8_t *flags, int n, int subs, int n_ints, double *w) {
+    if (n < 1 || subs < 1 || n_ints < 0) return ORC_EINVAL;
+    const int64_t row = (int64_t)n_ints * subs;
+    const int64_t P = (int64_t)n * (n + 1) / 2;
+    for (int j = 0; j < n_ints; ++j)
+        for (int64_t n1 = 0; n1 < n; ++n1)
+            for (int64_t n2 = 0; n2 <= n1; ++n2) {
+                int64_t both = 0;
+                for (int b = 0; b < subs; ++b) {
+                    const int64_t k = (int64_t)j * subs + b;
+                    if (flags[n1 * row + k] == 0 && flags[n2 * row + k] == 0) ++both;
+                }
+                w[(int64_t)j * P + n1 * (n1 + 1) / 2 + n2] = (double)both / (double)subs;
+            }
+    return ORC_OK;
+}
+
+/* Normalisation by the weights (Sec. 4.1): V_j[c][p] / w_j[p] where w > 0;
+ * a pair with w == 0 had a zeroed factor in every product, so its V is 0 and
+ * stays as it is.  vis: [n_ints][L][P][2] in place. */
+int orc_apply_weights(double *vis, const double *w, int n, int L, int n_ints) {
+    if (n < 1 || L < 1 || n_ints < 0) return ORC_EINVAL;
+    const int64_t P = (int64_t)n * (n + 1) / 2;
+    for (int j = 0; j < n_ints; ++j)
+        for (int c = 0; c < L; ++c)
+            for (int64_t p = 0; p < P; ++p) {
+                const double wt = w[(int64_t)j * P + p];
+                if (wt > 0.0) {
+                    double *v = vis + (((int64_t)j * L + c) * P + p) * 2;
+                    v[0] = v[0] / wt;
+                    v[1] = v[1] / wt;
+                }
+            }
     return ORC_OK;
 }

@@ -109,6 +109,26 @@ def tone_volts(n_inputs: int, n_samples: int, L: int, k0: int, amp: int, phases)
     return out
 
 
+_FLAG_STREAM = 0x6A09E667F3BCC909
+
+
+def zero_flags(n_inputs: int, n_sub: int, p: float, seed: int = MWAX_SEED) -> np.ndarray:
+    """Seeded zeroing flags [n_inputs][n_sub] uint8: 1 marks a 50 ms sub-block
+    whose packets were lost (probability p each)."""
+    idx = np.arange(n_inputs * n_sub, dtype=np.uint64)
+    return (uniform(idx, seed ^ _FLAG_STREAM) < p).astype(np.uint8).reshape(n_inputs, n_sub)
+
+
+def zero_subblocks(volts: np.ndarray, flags: np.ndarray, sub_len: int) -> np.ndarray:
+    """What the capture stage hands on: voltages [n][S][2] with every flagged
+    sub-block of sub_len samples set to zero (S = n_sub * sub_len)."""
+    n, S = volts.shape[:2]
+    if flags.shape != (n, S // sub_len) or S % sub_len:
+        raise ValueError("flags must cover the voltages in whole sub-blocks")
+    keep = np.repeat(flags == 0, sub_len, axis=1)
+    return (volts * keep[:, :, None]).astype(np.int8)
+
+
 # ---------------------------------------------------------------------------
 # Device generator (HIP).  Built by __graft_entry__.build() into libsynth.so.
 # ---------------------------------------------------------------------------

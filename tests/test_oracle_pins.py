@@ -494,3 +494,138 @@ def test_pins_catch_dropped_term(orc):
     assert not check_brute_force(bad, V, 1e-9)
     # transposed operand (x2 x1*) breaks the brute-force comparison as well
     assert not check_brute_force(np.conj(vis), V, 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Visibility weights (Sec. 4.1; zeroing flags of Sec. 2.4): per pair and
+# integration, the fraction of 50 ms sub-blocks populated in both inputs
+# ---------------------------------------------------------------------------
+def nested_losses(z, S, J):
+    """Input n loses the first z[n] sub-blocks of each of J integrations."""
+    flags = np.zeros((len(z), J * S), np.uint8)
+    for n, zn in enumerate(z):
+        for j in range(J):
+            flags[n, j * S: j * S + zn] = 1
+    return flags
+
+
+def nested_weights_ok(w, z, S):
+    """A pair keeps the sub-blocks after the later of its two losses."""
+    for j in range(w.shape[0]):
+        for a in range(len(z)):
+            for b in range(a + 1):
+                if w[j, a * (a + 1) // 2 + b] != (S - max(z[a], z[b])) / S:
+                    return False
+    return True
+
+
+def test_weights_nested_losses_closed_form(orc):
+    z, S = [0, 1, 5, 5, 7, 12, 19, 20, 3], 20
+    w = orc.vis_weights(nested_losses(z, S, 3), S)
+    assert w.shape == (3, 45)
+    assert nested_weights_ok(w, z, S)
+
+
+def test_weights_single_losses(orc):
+    # input n loses only sub-block n: cross pairs keep S - 2, autos S - 1
+    n, S = 7, 11
+    flags = np.zeros((n, S), np.uint8)
+    flags[np.arange(n), np.arange(n)] = 1
+    w = orc.vis_weights(flags, S)[0]
+    for a in range(n):
+        for b in range(a + 1):
+            assert w[a * (a + 1) // 2 + b] == ((S - 1) / S if a == b else (S - 2) / S)
+
+
+def test_weights_are_the_gram_matrix_of_the_populated_masks(orc):
+    # counting sub-blocks populated in both inputs is the product A A^T of the
+    # 0/1 populated matrix with itself (numpy matmul, exact on small integers)
+    n, S, J = 13, 37, 4
+    flags = synth.zero_flags(n, J * S, 0.2, seed=5)
+    w = orc.vis_weights(flags, S)
+    r, c = np.tril_indices(n)
+    order = np.argsort(r * (r + 1) // 2 + c)
+    for j in range(J):
+        A = (flags[:, j * S:(j + 1) * S] == 0).astype(np.float64)
+        G = A @ A.T
+        assert np.array_equal(w[j], G[r[order], c[order]] / S)
+
+
+def test_weights_from_the_samples_themselves(orc):
+    # the weight is the fraction of the integration's samples present in both
+    # signal paths: counted sample by sample on a zeroed tone (whose samples are
+    # never 0 unless zeroed)
+    n, L, sub_len, S_int, J = 4, 8, 16, 5, 2
+    flags = synth.zero_flags(n, J * S_int, 0.35, seed=9)
+    v = synth.zero_subblocks(synth.tone_volts(n, J * S_int * sub_len, L, L // 4, 7, [0, 1, 2, 3]),
+                             flags, sub_len)
+    w = orc.vis_weights(flags, S_int)
+    present = np.any(v != 0, axis=2)
+    span = S_int * sub_len
+    for j in range(J):
+        for a in range(n):
+            for b in range(a + 1):
+                both = sum(1 for s in range(j * span, (j + 1) * span) if present[a, s] and present[b, s])
+                assert w[j, a * (a + 1) // 2 + b] == both / span
+
+
+def test_normalised_tone_recovers_the_unflagged_closed_form(orc):
+    # P4 tone with zeroed sub-blocks (whole spectra each): before normalisation
+    # V[c0] = w T L^2 A^2 i^(p1 - p2); after it, the closed form of the
+    # unflagged tone; pairs without a common sub-block stay 0
+    n, L, sub_len, S_int, J, amp = 5, 8, 16, 5, 2, 11
+    phases = [0, 3, 1, 2, 1]
+    T = S_int * sub_len // L
+    flags = synth.zero_flags(n, J * S_int, 0.3, seed=4)
+    flags[2, :S_int] = 1                           # input 2 lost the whole first integration
+    v = synth.zero_subblocks(synth.tone_volts(n, J * S_int * sub_len, L, L // 4, amp, phases),
+                             flags, sub_len)
+    vis = orc.fx_correlate(v, L, T)
+    w = orc.vis_weights(flags, S_int)
+    normed = orc.apply_weights(vis, w)
+    c0 = (L // 4 + L // 2) % L
+    peak = T * L * L * amp * amp
+    assert np.count_nonzero(w == 0) > 0 and np.count_nonzero((w > 0) & (w < 1)) > 0
+    for j in range(J):
+        for a in range(n):
+            for b in range(a + 1):
+                p = a * (a + 1) // 2 + b
+                want = peak * (1j ** ((phases[a] - phases[b]) % 4))
+                assert abs(vis[j, c0, p] - w[j, p] * want) <= 1e-9 * peak
+                if w[j, p] > 0:
+                    assert abs(normed[j, c0, p] - want) <= 1e-9 * peak
+                else:
+                    assert normed[j, c0, p] == 0
+                others = np.delete(normed[j, :, p], c0)
+                assert np.all(np.abs(others) <= 1e-9 * peak)
+
+
+def test_weight_pins_catch_planted_slips(orc):
+    # slips planted in copies of the oracle's weights: counting sub-blocks
+    # lost in both inputs, populated in either, or in the first input only;
+    # dividing by the sub-blocks of the whole flag row
+    z, S, J = [0, 1, 5, 5, 7, 12, 19, 20, 3], 20, 2
+    flags = nested_losses(z, S, J)
+    good = orc.vis_weights(flags, S)
+    assert nested_weights_ok(good, z, S)
+    n = len(z)
+    lost_both = np.zeros_like(good)
+    either = np.zeros_like(good)
+    first = np.zeros_like(good)
+    for j in range(J):
+        f = flags[:, j * S:(j + 1) * S].astype(bool)
+        for a in range(n):
+            for b in range(a + 1):
+                p = a * (a + 1) // 2 + b
+                lost_both[j, p] = np.sum(f[a] & f[b]) / S
+                either[j, p] = np.sum(~f[a] | ~f[b]) / S
+                first[j, p] = np.sum(~f[a]) / S
+    for bad in (lost_both, either, first, good * S / (J * S)):
+        assert not nested_weights_ok(bad, z, S)
+
+
+def test_apply_weights_divides_only_where_weighted(orc):
+    vis = np.array([[[2 + 4j, -3 + 1j, 0j]]])
+    w = np.array([[0.5, 0.0, 0.25]])
+    out = orc.apply_weights(vis, w)
+    assert out[0, 0, 0] == 4 + 8j and out[0, 0, 1] == -3 + 1j and out[0, 0, 2] == 0
