@@ -115,7 +115,7 @@ def copy_bandwidth():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="channel", choices=["channel", "batch", "stream"],
+    ap.add_argument("--workload", default="channel", choices=["channel", "batch", "stream", "weights"],
                     help="channel: one coarse channel, 256 tiles, 8 s (the headline metric); "
                          "batch: 24 uneven instances as one batch; stream: 24 channels streamed in 8 s blocks")
     ap.add_argument("--stream-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
@@ -233,6 +233,98 @@ def main_batch(args):
     print(json.dumps(line), flush=True)
 
 
+# Weights workload: one 8 s block of one coarse channel at 256 tiles, 2 s
+# integrations (four visibility sets of 128 channels x 131,328 pairs), 50 ms
+# zeroing flags (160 per input per block, 1 % lost, input 0 lost throughout).
+WEIGHTS_INT_S, WEIGHTS_SUB_S, WEIGHTS_LOSS = 2.0, 0.05, 0.01
+
+
+def main_weights(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    n_in = 2 * N_TILES
+    P = n_in * (n_in + 1) // 2
+    n_ints = int(round(SECONDS / WEIGHTS_INT_S))
+    subs = int(round(WEIGHTS_INT_S / WEIGHTS_SUB_S))
+    flags_h = synth.zero_flags(n_in, n_ints * subs, WEIGHTS_LOSS, seed=synth.MWAX_SEED + 7)
+    flags_h[0, :] = 1
+    flags = torch.from_numpy(flags_h).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(synth.MWAX_SEED + 8)
+    vis = torch.randn((n_ints, L, P), dtype=torch.complex64, device="cuda", generator=gen)
+    w = torch.empty((n_ints, P), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mwax.vis_weights(flags, subs, out=w, stream=stream)
+        mwax.apply_weights(vis, w, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # per-kernel durations: HIP events on the stream the kernels run on
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e in ev:
+        e[0].record(stream)
+        mwax.vis_weights(flags, subs, out=w, stream=stream)
+        e[1].record(stream)
+        mwax.apply_weights(vis, w, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    w_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
+    a_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / len(ev)
+    a_bytes = 2 * n_ints * L * P * 8 + n_ints * P * 4
+    w_bytes = n_in * n_ints * subs + n_ints * P * 4
+    a_gbs = a_bytes / (a_ms / 1e3) / 1e9
+    w_gbs = w_bytes / (w_ms / 1e3) / 1e9
+    step_bytes = a_bytes + w_bytes
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        vis_h = vis.cpu().numpy()
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            wo = oracle.vis_weights(flags_h, subs)
+            oracle.apply_weights(vis_h, wo)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or reps >= 32:
+                break
+        cpu = {"value": reps * step_bytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole step (weights of {n_in} inputs x {n_ints * subs} sub-blocks, normalisation "
+                         f"of {n_ints} x {L} x {P} visibilities) {reps} times, {dt:.1f} s wall"}
+    line = {
+        "metric": "visibility weights + normalisation throughput (algorithmic HBM bytes/s)",
+        "value": step_bytes / (ms / 1e3) / 1e9, "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256 tiles x 2 pols, 1 coarse channel, 128 fine channels, one 8 s block: "
+                               "four 2 s visibility sets, 50 ms zeroing flags (1 % lost, input 0 lost)",
+                   "n_inputs": n_in, "n_ints": n_ints, "subs_per_int": subs, "bytes_per_step": step_bytes},
+        "rtf": round(SECONDS / (ms / 1e3), 1),
+        "roofline": {"kernel": "apply_weights_kernel", "bound": "hbm", "achieved": round(a_gbs, 1),
+                     "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(a_gbs / PEAK["hbm_gbs"], 4),
+                     "traffic": None, "avg_launch_ms": round(a_ms, 4), "bytes_per_launch": a_bytes},
+        "roofline_other": {"kernel": "vis_weights_kernel", "bound": "hbm", "achieved": round(w_gbs, 1),
+                           "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(w_gbs / PEAK["hbm_gbs"], 4),
+                           "avg_launch_ms": round(w_ms, 4), "bytes_per_launch": w_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main_stream(args):
     """Streaming: 24 coarse channels x 256 tiles, continuous 8 s blocks, 2 s
     integrations on the device, int8 X-engine, admission by HBM budget.
@@ -342,6 +434,8 @@ def main():
         return main_batch(args)
     if args.workload == "stream":
         return main_stream(args)
+    if args.workload == "weights":
+        return main_weights(args)
 
     import torch
 

@@ -376,6 +376,34 @@ mwax_status mwax_stream_poll(mwax_stream s, int32_t wait_ms, mwax_block_done *ou
  * it is still in the ring (the out_depth most recent); MWAX_E_STATE if not. */
 mwax_status mwax_stream_vis(mwax_stream s, int32_t channel, int64_t j, void **d_vis);
 
+/* ---- visibility weights (Sec. 4.1; zeroing flags of Sec. 2.4; weight table
+ * of Sec. 2.7) ----
+ *
+ * The capture stage zeroes the samples of lost or excised packets and flags,
+ * per signal path, each 50 ms sub-block that was zeroed.  The weight of input
+ * pair (n1, n2) in an integration is the fraction of its sub-blocks that are
+ * populated in both inputs, one value per pair for all fine channels.  An
+ * integration must span a whole number of sub-blocks (subs_per_int; 8 s = 160
+ * sub-blocks).  Both calls enqueue on hip_stream (NULL = the null stream) and
+ * need no plan and no workspace.
+ *
+ * mwax_vis_weights: d_flags = [n_inputs][n_ints * subs_per_int] uint8, device,
+ * nonzero = that input's sub-block was zeroed (row n holds integration j's
+ * sub-blocks at j * subs_per_int ..).  d_weights = [n_ints][P] float32, device,
+ * packed like the visibilities: w = (populated-in-both count) / subs_per_int,
+ * divided in FP32 (correctly rounded).  n_inputs 1..2048, subs_per_int >= 1;
+ * n_ints == 0 enqueues nothing.  MWAX_E_INVAL on bad sizes, NULL or misaligned
+ * pointers (weights 4-byte aligned). */
+mwax_status mwax_vis_weights(const uint8_t *d_flags, int32_t n_inputs, int32_t subs_per_int, int32_t n_ints,
+                             float *d_weights, void *hip_stream);
+/* mwax_apply_weights: normalise CHAN_TRI visibilities in place, d_vis =
+ * [n_ints][n_chan][P] complex64, device: V /= w[j][p] (FP32, correctly
+ * rounded) where w > 0.  Where w == 0 every product of the sum had a zeroed
+ * sample, so V is 0 and is left unchanged.  d_weights as written by
+ * mwax_vis_weights.  Sizes as above, n_chan >= 1; d_vis 8-byte aligned. */
+mwax_status mwax_apply_weights(void *d_vis, const float *d_weights, int32_t n_inputs, int32_t n_chan,
+                               int32_t n_ints, void *hip_stream);
+
 /* Message for the last error of the calling thread (empty if none). */
 const char *mwax_last_error(void);
 

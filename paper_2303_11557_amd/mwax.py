@@ -31,7 +31,7 @@ EXPORTS = (
     "mwax_batch_set_timing", "mwax_batch_kernel_time", "mwax_batch_sync",
     "mwax_stream_create", "mwax_stream_destroy", "mwax_stream_get_info", "mwax_stream_plan",
     "mwax_stream_now", "mwax_stream_acquire", "mwax_stream_copy_in", "mwax_stream_submit",
-    "mwax_stream_poll", "mwax_stream_vis",
+    "mwax_stream_poll", "mwax_stream_vis", "mwax_vis_weights", "mwax_apply_weights",
 )
 
 
@@ -141,6 +141,8 @@ def lib():
             "mwax_stream_submit": [vp, i32, i32, ctypes.c_double],
             "mwax_stream_poll": [vp, i32, P(BlockDone), i32, P(i32)],
             "mwax_stream_vis": [vp, i32, i64, P(vp)],
+            "mwax_vis_weights": [vp, i32, i32, i32, vp, vp],
+            "mwax_apply_weights": [vp, vp, i32, i32, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -486,6 +488,40 @@ class Stream:
         ptr = ctypes.c_void_p()
         _check(lib().mwax_stream_vis(self.h, int(channel), int(j), ctypes.byref(ptr)))
         return ptr.value
+
+
+def vis_weights(flags, subs_per_int, out=None, stream=None):
+    """Occupancy weights [n_ints][P] float32 from zeroing flags
+    [n_inputs][n_ints * subs_per_int] uint8 (nonzero = sub-block zeroed), both
+    on the device (Sec. 4.1)."""
+    import torch
+    assert flags.is_cuda and flags.dtype == torch.uint8 and flags.is_contiguous() and flags.dim() == 2
+    n_in, n_sub = flags.shape
+    subs = int(subs_per_int)
+    assert subs >= 1 and n_sub % subs == 0, "flags must hold a whole number of integrations"
+    n_ints = n_sub // subs
+    if out is None:
+        out = torch.empty((n_ints, n_in * (n_in + 1) // 2), dtype=torch.float32, device=flags.device)
+    assert out.is_contiguous() and out.dtype == torch.float32 and out.numel() >= n_ints * (n_in * (n_in + 1) // 2)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().mwax_vis_weights(ctypes.c_void_p(flags.data_ptr()), n_in, subs, n_ints,
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def apply_weights(vis, weights, stream=None):
+    """Normalise CHAN_TRI visibilities [n_ints][L][P] complex64 in place by the
+    weights [n_ints][P] (V / w where w > 0); returns vis."""
+    import torch
+    assert vis.is_cuda and vis.dtype == torch.complex64 and vis.is_contiguous() and vis.dim() == 3
+    n_ints, L, P = vis.shape
+    n_in = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    assert n_in * (n_in + 1) // 2 == P, "P is not a triangular number"
+    assert weights.is_contiguous() and weights.dtype == torch.float32 and tuple(weights.shape) == (n_ints, P)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().mwax_apply_weights(ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+                                    n_in, L, n_ints, ctypes.c_void_p(st.cuda_stream)))
+    return vis
 
 
 def device_view(ptr, shape, dtype):

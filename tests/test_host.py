@@ -191,3 +191,22 @@ def test_stream_struct_layouts():
     assert ctypes.sizeof(mwax.StreamConfig) == 4 + 4 + ctypes.sizeof(mwax.Config) + 8 + 8
     assert ctypes.sizeof(mwax.BlockDone) == 4 + 4 + 8 + 8 + 4 + 4 + 8 * 3
     assert ctypes.sizeof(mwax.StreamInfo) == 4 + 4 + 8 + 8 + 8 + 8 + 8
+
+
+def test_weight_arguments_are_checked_without_a_device(lib):
+    vp = ctypes.c_void_p
+    fake = vp(4096)          # never dereferenced: every call below fails its checks first
+    assert lib.mwax_vis_weights(fake, 0, 4, 1, fake, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(fake, 2049, 4, 1, fake, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(fake, 8, 0, 1, fake, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(fake, 8, 4, -1, fake, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(None, 8, 4, 1, fake, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(fake, 8, 4, 1, vp(4098), None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_vis_weights(None, 8, 4, 0, None, None) == mwax.MWAX_OK      # nothing to do
+    assert lib.mwax_apply_weights(fake, fake, 0, 16, 1, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_apply_weights(fake, fake, 8, 0, 1, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_apply_weights(fake, fake, 8, 16, -2, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_apply_weights(None, fake, 8, 16, 1, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_apply_weights(vp(4100), fake, 8, 16, 1, None) == mwax.MWAX_E_INVAL
+    assert b"aligned" in lib.mwax_last_error()
+    assert lib.mwax_apply_weights(None, None, 8, 16, 0, None) == mwax.MWAX_OK
