@@ -33,14 +33,15 @@ PEAK = {  # MI355X published dense peaks
 }
 N_TILES, L, SECONDS, F_S = 256, 128, 8.0, 1.28e6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_channel_256tiles_8s.json")
+TRAFFIC_WEIGHTS_FILE = os.path.join(ROOT, "profiles", "traffic_weights_256tiles_8s.json")
 
 
-def measured_traffic(key):
+def measured_traffic(key, path=TRAFFIC_FILE):
     """HBM bytes per launch of kernel `key` from the committed counter summary, or
     None when there is none or the kernel's source has changed since it was taken."""
     from paper_2303_11557_amd import profiling
     try:
-        ent = json.load(open(TRAFFIC_FILE)).get(key)
+        ent = json.load(open(path)).get(key)
     except (OSError, ValueError):
         return None
     if not ent or ent.get("source_sha") != profiling.source_sha(key.split("_")[0]):
@@ -257,6 +258,8 @@ def main_weights(args):
     flags = torch.from_numpy(flags_h).cuda()
     gen = torch.Generator(device="cuda").manual_seed(synth.MWAX_SEED + 8)
     vis = torch.randn((n_ints, L, P), dtype=torch.complex64, device="cuda", generator=gen)
+    if args.copy_probe:
+        copy_bandwidth()                 # a 4 GiB copy of known size scales the HBM counters
     w = torch.empty((n_ints, P), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -316,9 +319,11 @@ def main_weights(args):
         "rtf": round(SECONDS / (ms / 1e3), 1),
         "roofline": {"kernel": "apply_weights_kernel", "bound": "hbm", "achieved": round(a_gbs, 1),
                      "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(a_gbs / PEAK["hbm_gbs"], 4),
-                     "traffic": None, "avg_launch_ms": round(a_ms, 4), "bytes_per_launch": a_bytes},
+                     "traffic": measured_traffic("weights_apply", TRAFFIC_WEIGHTS_FILE),
+                     "avg_launch_ms": round(a_ms, 4), "bytes_per_launch": a_bytes},
         "roofline_other": {"kernel": "vis_weights_kernel", "bound": "hbm", "achieved": round(w_gbs, 1),
                            "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(w_gbs / PEAK["hbm_gbs"], 4),
+                           "traffic": measured_traffic("weights_occupancy", TRAFFIC_WEIGHTS_FILE),
                            "avg_launch_ms": round(w_ms, 4), "bytes_per_launch": w_bytes},
         "cpu_baseline": cpu,
     }

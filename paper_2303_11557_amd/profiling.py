@@ -29,6 +29,7 @@ SOURCES = {
     "fengine": os.path.join(HERE, "csrc", "fengine.hip"),
     "xengine": os.path.join(HERE, "csrc", "xengine.hip"),
     "pack": os.path.join(HERE, "csrc", "pack.hip"),
+    "weights": os.path.join(HERE, "csrc", "weights.hip"),
 }
 PREC = {"0": "fp32", "1": "fp16", "2": "int8"}
 
@@ -66,6 +67,10 @@ def kernel_key(name):
         return "xengine_fp32"
     if s.startswith("pack_"):
         return s.split("<")[0]
+    if s.startswith("apply_weights_kernel"):
+        return "weights_apply"
+    if s.startswith("vis_weights_kernel"):
+        return "weights_occupancy"
     return None
 
 
