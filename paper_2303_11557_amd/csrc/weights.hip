@@ -24,6 +24,8 @@ namespace {
 constexpr int kWBlock = 64;          // inputs per side of a pair block
 constexpr int kWWords = 32;          // mask words per LDS pass (1024 sub-blocks)
 constexpr int kMaxInputs = 2048;     // n_inputs of a 1024-tile array
+constexpr int kRowBatch = 8;         // flag rows a wave loads before their ballots
+static_assert(2 * kWBlock % (4 * kRowBatch) == 0, "row batches must tile the 128 rows");
 
 __global__ __launch_bounds__(256) void vis_weights_kernel(const uint8_t *__restrict__ flags, int n_in,
                                                           int subs, int n_ints, float *__restrict__ w) {
@@ -44,18 +46,29 @@ __global__ __launch_bounds__(256) void vis_weights_kernel(const uint8_t *__restr
         for (int w0 = 0; w0 < W; w0 += kWWords) {
             __syncthreads();
             // one wave per input row: 64 lanes read 64 consecutive flags and a
-            // ballot of "populated" is two mask words
+            // ballot of "populated" is two mask words.  A wave owns the rows
+            // r = wave (mod 4) and loads 8 of them before their ballots, so the
+            // loads overlap; addresses are clamped into the flag array.
             const int nw = min(kWWords, W - w0);
             const int lane = tid & 63, wave = tid >> 6;
-            for (int r = wave; r < 2 * kWBlock; r += 4) {
-                const int n = r < kWBlock ? bi * kWBlock + r : bj * kWBlock + (r - kWBlock);
-                const uint8_t *f = flags + (int64_t)min(n, n_in - 1) * row_len + (int64_t)j * subs;
-                for (int k = 0; k < nw; k += 2) {
-                    const int b = (w0 + k) * 32 + lane;
-                    const bool pop = n < n_in && b < subs && f[min(b, subs - 1)] == 0;
-                    const uint64_t m = __ballot(pop);
-                    if (lane == 0) mask[r][k] = (uint32_t)m;
-                    if (lane == 1) mask[r][k + 1] = (uint32_t)(m >> 32);
+            for (int k = 0; k < nw; k += 2) {
+                const int b = (w0 + k) * 32 + lane;
+                const int bc = min(b, subs - 1);
+                for (int r0 = wave; r0 < 2 * kWBlock; r0 += 4 * kRowBatch) {
+                    bool pop[kRowBatch];
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) {
+                        const int r = r0 + 4 * u;
+                        const int n = r < kWBlock ? bi * kWBlock + r : bj * kWBlock + (r - kWBlock);
+                        const uint8_t v = flags[(int64_t)min(n, n_in - 1) * row_len + (int64_t)j * subs + bc];
+                        pop[u] = (n < n_in) & (b < subs) & (v == 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kRowBatch; ++u) {
+                        const uint64_t m = __ballot(pop[u]);
+                        if (lane == 0) mask[r0 + 4 * u][k] = (uint32_t)m;
+                        if (lane == 1) mask[r0 + 4 * u][k + 1] = (uint32_t)(m >> 32);
+                    }
                 }
             }
             __syncthreads();
