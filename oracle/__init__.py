@@ -11,6 +11,8 @@ module only marshals numpy arrays.  Conventions (Morrison et al. 2023):
   samples, channels fftshifted so DC sits at c = L/2 (Sec. 2.6).
 * X step (Sec. 2.5.2): V_j[c][n1,n2] = sum_{m in j} X_n1[m,c] conj(X_n2[m,c])
   for n1 >= n2, packed at n1 (n1+1)/2 + n2 (Sec. 2.7).
+* Channel averaging (Sec. 2.6): centre-symmetric means of F fine channels
+  (F + 1 with half-weight ends for even F), DC left out of the centre one.
 * Weights (Sec. 4.1): fraction of an integration's 50 ms sub-blocks populated
   in both inputs of a pair; optional normalisation V / w.
 """
@@ -71,9 +73,10 @@ def _load():
         lib.orc_vis_weights.argtypes = [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, _c_f64p]
         lib.orc_apply_weights.argtypes = [_c_f64p, _c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.orc_fscrunch.argtypes = [_c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_f64p]
         for f in ("orc_dft", "orc_fft", "orc_channelise", "orc_correlate", "orc_correlate_full",
                   "orc_correlate_i64", "orc_requantise", "orc_calibrate", "orc_round_fp16",
-                  "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights"):
+                  "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights", "orc_fscrunch"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -234,6 +237,14 @@ def fx_correlate(volts: np.ndarray, L: int, T: int, threads: int = 1) -> np.ndar
     return correlate(spec, T, threads)
 
 
+def _inputs_of(P: int) -> int:
+    """Number of inputs n with n (n + 1) / 2 = P pairs."""
+    n = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    if n * (n + 1) // 2 != P:
+        raise ValueError(f"{P} is not a pair count n (n + 1) / 2")
+    return n
+
+
 def vis_weights(flags: np.ndarray, subs_per_int: int) -> np.ndarray:
     """Occupancy weights (Sec. 4.1): flags [n][n_ints * subs] (nonzero = zeroed
     sub-block) -> [n_ints][P] fraction of sub-blocks populated in both inputs."""
@@ -255,7 +266,19 @@ def apply_weights(vis, w) -> np.ndarray:
     wa = np.ascontiguousarray(w, dtype=np.float64)
     if wa.shape != (n_ints, P):
         raise ValueError("weights must be [n_ints][P]")
-    n = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    n = _inputs_of(P)
     _check(_load().orc_apply_weights(_ptr(vp, _c_f64p), _ptr(wa, _c_f64p), n, L, n_ints),
            "apply_weights")
     return _to_complex(vp)
+
+
+def fscrunch(vis, F: int) -> np.ndarray:
+    """Channel averaging (Sec. 2.6): [n_ints][L][P] -> [n_ints][L/F][P]."""
+    vp = _as_pairs(np.asarray(vis, dtype=np.complex128))
+    n_ints, L, P = vp.shape[:3]
+    if F < 1 or L % F:
+        raise ValueError("F must divide L")
+    n = _inputs_of(P)
+    out = np.empty((n_ints, L // F, P, 2), np.float64)
+    _check(_load().orc_fscrunch(_ptr(vp, _c_f64p), n, L, n_ints, int(F), _ptr(out, _c_f64p)), "fscrunch")
+    return _to_complex(out)

@@ -22,6 +22,8 @@
  *              V_j[c][n1,n2] = sum_{m in j} X_n1[m,c] conj(X_n2[m,c])
  *   Output   (Sec. 2.7): lower triangle packed row-major,
  *              index(n1,n2) = n1 (n1+1) / 2 + n2.
+ *   Averaging (Sec. 2.6): centre-symmetric means of F fine channels (F + 1
+ *            with half-weight ends for even F), DC left out of the centre.
  *   Weights  (Sec. 4.1): per pair and integration, the fraction of 50 ms
  *            sub-blocks populated in both inputs; optional V / w.
  *
@@ -449,6 +451,50 @@ int orc_apply_weights(double *vis, const double *w, int n, int L, int n_ints) {
                     v[0] = v[0] / wt;
                     v[1] = v[1] / wt;
                 }
+            }
+    return ORC_OK;
+}
+
+/* -------------------------------------------------------------------------
+ * Channel averaging (Sec. 2.6).  L fine channels (DC at c = L/2) are averaged
+ * by F into N = L / F output channels arranged centre-symmetrically: output
+ * channel o is centred (o - N/2) * F channels from DC (N/2 rounded down).
+ *   F odd : the F channels at offsets d = -(F-1)/2 .. (F-1)/2, weight 1;
+ *   F even: the F + 1 channels at d = -F/2 .. F/2, the two outermost weighted
+ *           0.5, so that a channel boundary falls on a channel centre shared
+ *           half and half by the two neighbours.
+ * The centre output channel leaves out the DC channel and is divided by the
+ * remaining weight (F - 1); every other channel by F.  With N even the
+ * outermost output channel is the half channel at the coarse-channel edges
+ * (its channels wrap round +-f_s/2).  F = 1 returns the input unchanged.
+ * vis: [n_ints][L][P][2];  out: [n_ints][L/F][P][2].
+ * ------------------------------------------------------------------------- */
+int orc_fscrunch(const double *vis, int n, int L, int n_ints, int F, double *out) {
+    if (n < 1 || L < 1 || n_ints < 0 || F < 1 || L % F) return ORC_EINVAL;
+    const int64_t P = (int64_t)n * (n + 1) / 2;
+    const int N = L / F, oc = N / 2;
+    for (int j = 0; j < n_ints; ++j)
+        for (int o = 0; o < N; ++o)
+            for (int64_t p = 0; p < P; ++p) {
+                double re = 0.0, im = 0.0, wsum = 0.0;
+                const int half = F / 2;
+                for (int d = -half; d <= half; ++d) {
+                    if (F == 1) {
+                        /* a single channel, no exclusion */
+                    } else if (o == oc && d == 0) {
+                        continue;                        /* DC left out of the centre channel */
+                    }
+                    double w = 1.0;
+                    if (F % 2 == 0 && (d == -half || d == half)) w = 0.5;
+                    const int c = ((L / 2 + (o - oc) * F + d) % L + L) % L;
+                    const double *v = vis + (((int64_t)j * L + c) * P + p) * 2;
+                    re += w * v[0];
+                    im += w * v[1];
+                    wsum += w;
+                }
+                double *y = out + (((int64_t)j * N + o) * P + p) * 2;
+                y[0] = re / wsum;
+                y[1] = im / wsum;
             }
     return ORC_OK;
 }

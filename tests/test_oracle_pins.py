@@ -629,3 +629,112 @@ def test_apply_weights_divides_only_where_weighted(orc):
     w = np.array([[0.5, 0.0, 0.25]])
     out = orc.apply_weights(vis, w)
     assert out[0, 0, 0] == 4 + 8j and out[0, 0, 1] == -3 + 1j and out[0, 0, 2] == 0
+
+
+# ---------------------------------------------------------------------------
+# Channel averaging (Sec. 2.6): centre-symmetric output channels of F fine
+# channels, half-weight shared boundaries for even F, DC left out of the centre
+# ---------------------------------------------------------------------------
+AVG_CASES = [(16, 1), (16, 2), (16, 4), (16, 16), (20, 5), (30, 3), (32, 8), (12, 6)]
+
+
+def band_weights(L, F):
+    """weights[o][c] from the band edges in frequency: output channel o spans
+    offsets (o - N/2) F +- F/2 from DC (in fine channels, modulo the coarse
+    bandwidth L); a fine channel strictly inside counts 1, one centred on an
+    edge 1/2 (both halves when the band spans the whole coarse channel, F = L,
+    and its two edges meet at +-f_s/2), the DC channel 0 in the centre output
+    channel."""
+    N, oc = L // F, (L // F) // 2
+    w = np.zeros((N, L))
+    for o in range(N):
+        for c in range(L):
+            delta = ((c - L // 2 - (o - oc) * F + L // 2) % L) - L // 2
+            for x in (delta - L, delta, delta + L):
+                if F == 1:
+                    w[o, c] += 1.0 if x == 0 else 0.0
+                elif 2 * abs(x) < F:
+                    w[o, c] += 1.0
+                elif 2 * abs(x) == F:
+                    w[o, c] += 0.5
+            if F > 1 and o == oc and c == L // 2:
+                w[o, c] = 0.0
+    return w
+
+
+def averaging_ok(out, vis, L, F):
+    w = band_weights(L, F)
+    want = np.einsum("oc,jcp->jop", w, vis) / w.sum(axis=1)[None, :, None]
+    return np.allclose(out, want, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("L,F", AVG_CASES)
+def test_averaging_matches_the_band_edges(orc, L, F):
+    r = rng(L * 31 + F)
+    vis = r.standard_normal((2, L, 6)) + 1j * r.standard_normal((2, L, 6))
+    assert averaging_ok(orc.fscrunch(vis, F), vis, L, F)
+
+
+@pytest.mark.parametrize("L,F", AVG_CASES)
+def test_averaging_keeps_a_flat_spectrum(orc, L, F):
+    vis = np.full((1, L, 3), 5.0 - 2.0j)
+    assert np.allclose(orc.fscrunch(vis, F), 5.0 - 2.0j, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("L,F", [(c[0], c[1]) for c in AVG_CASES if c[1] > 1])
+def test_averaging_counts_every_frequency_once_except_dc(orc, L, F):
+    # Sec. 2.6: every frequency contributes equally to the total power; the
+    # per-channel weights (F, or F - 1 at the centre) undo the means
+    r = rng(L + F)
+    vis = r.standard_normal((1, L, 10)) + 1j * r.standard_normal((1, L, 10))
+    out = orc.fscrunch(vis, F)
+    N = L // F
+    W = np.full(N, float(F))
+    W[N // 2] = F - 1
+    total = np.einsum("o,jop->jp", W, out)
+    assert np.allclose(total, vis.sum(axis=1) - vis[:, L // 2], rtol=1e-13, atol=1e-12)
+
+
+def test_averaging_boundary_response_is_3db_down(orc):
+    # even F: a signal in the fine channel on a boundary between two output
+    # channels lands at half weight in each (Sec. 2.6: 3 dB at the boundaries)
+    L, F = 32, 8
+    N = L // F
+    for c in range(L):
+        vis = np.zeros((1, L, 1), complex)
+        vis[0, c, 0] = 1.0
+        resp = orc.fscrunch(vis, F)[0, :, 0].real * np.where(np.arange(N) == N // 2, F - 1, F)
+        delta = (c - L // 2) % F
+        if c == L // 2:
+            assert np.all(resp == 0)
+        elif delta == F // 2:
+            assert sorted(resp[resp != 0]) == [0.5, 0.5]
+            assert 10 * math.log10(0.5) == pytest.approx(-3.0103, abs=1e-4)
+        else:
+            assert sorted(resp[resp != 0]) == [1.0]
+
+
+def test_averaging_pins_catch_planted_slips(orc):
+    L, F = 32, 8
+    r = rng(3)
+    vis = r.standard_normal((1, L, 6)) + 1j * r.standard_normal((1, L, 6))
+    good = orc.fscrunch(vis, F)
+    assert averaging_ok(good, vis, L, F)
+    N, oc = L // F, (L // F) // 2
+
+    def slip(keep_dc=False, full_ends=False, centre=oc):
+        out = np.zeros_like(good)
+        for o in range(N):
+            acc, ws = 0, 0
+            for d in range(-F // 2, F // 2 + 1):
+                if o == centre and d == 0 and not keep_dc:
+                    continue
+                w = 1.0 if full_ends or abs(d) < F // 2 else 0.5
+                acc = acc + w * vis[:, (L // 2 + (o - centre) * F + d) % L]
+                ws += w
+            out[:, o] = acc / ws
+        return out
+
+    assert averaging_ok(slip(), vis, L, F)              # the slip helper itself is right
+    for bad in (slip(keep_dc=True), slip(full_ends=True), slip(centre=oc - 1)):
+        assert not averaging_ok(bad, vis, L, F)
