@@ -116,7 +116,7 @@ def copy_bandwidth():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="channel", choices=["channel", "batch", "stream", "weights"],
+    ap.add_argument("--workload", default="channel", choices=["channel", "batch", "stream", "weights", "fscrunch"],
                     help="channel: one coarse channel, 256 tiles, 8 s (the headline metric); "
                          "batch: 24 uneven instances as one batch; stream: 24 channels streamed in 8 s blocks")
     ap.add_argument("--stream-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
@@ -330,6 +330,83 @@ def main_weights(args):
     print(json.dumps(line), flush=True)
 
 
+# Averaging workload: one 8 s integration of one coarse channel at 256 tiles
+# with 1024 fine channels (1.25 kHz), averaged by 8 to 128 channels of 10 kHz.
+AVG_L, AVG_F = 1024, 8
+TRAFFIC_AVG_FILE = os.path.join(ROOT, "profiles", "traffic_fscrunch_256tiles_8s.json")
+
+
+def main_fscrunch(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    n_in = 2 * N_TILES
+    P = n_in * (n_in + 1) // 2
+    N = AVG_L // AVG_F
+    gen = torch.Generator(device="cuda").manual_seed(synth.MWAX_SEED + 10)
+    vis = torch.randn((1, AVG_L, P), dtype=torch.complex64, device="cuda", generator=gen)
+    out = torch.empty((1, N, P), dtype=torch.complex64, device="cuda")
+    if args.copy_probe:
+        copy_bandwidth()                 # a 4 GiB copy of known size scales the HBM counters
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        mwax.fscrunch(vis, AVG_F, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mwax.fscrunch(vis, AVG_F, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        mwax.fscrunch(vis, AVG_F, out=out, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    nbytes = AVG_L * P * 8 + N * P * 8
+    gbs = nbytes / (k_ms / 1e3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_s = 128                        # pairs of the first 128 inputs: the first 8,256 of the triangle
+        P_s = n_s * (n_s + 1) // 2
+        sample = np.ascontiguousarray(vis[:, :, :P_s].cpu().numpy())
+        t0, reps = time.perf_counter(), 0
+        while True:
+            oracle.fscrunch(sample, AVG_F)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or reps >= 64:
+                break
+        s_bytes = AVG_L * P_s * 8 + N * P_s * 8
+        cpu = {"value": reps * s_bytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the pairs of the first {n_s} inputs ({P_s} of {P}) x {AVG_L} channels, averaged by "
+                         f"{AVG_F}, {reps} times, {dt:.1f} s wall"}
+    line = {
+        "metric": "channel averaging throughput (algorithmic HBM bytes/s)",
+        "value": nbytes / (ms / 1e3) / 1e9, "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256 tiles x 2 pols, 1 coarse channel, one 8 s integration of 1024 fine channels "
+                               "(1.25 kHz) averaged by 8 to 128 x 10 kHz",
+                   "n_inputs": n_in, "fine_channels": AVG_L, "fscrunch": AVG_F, "bytes_per_step": nbytes},
+        "rtf": round(SECONDS / (ms / 1e3), 1),
+        "roofline": {"kernel": "fscrunch_kernel", "bound": "hbm", "achieved": round(gbs, 1),
+                     "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(gbs / PEAK["hbm_gbs"], 4),
+                     "traffic": measured_traffic("average_fscrunch", TRAFFIC_AVG_FILE),
+                     "avg_launch_ms": round(k_ms, 4), "bytes_per_launch": nbytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main_stream(args):
     """Streaming: 24 coarse channels x 256 tiles, continuous 8 s blocks, 2 s
     integrations on the device, int8 X-engine, admission by HBM budget.
@@ -441,6 +518,8 @@ def main():
         return main_stream(args)
     if args.workload == "weights":
         return main_weights(args)
+    if args.workload == "fscrunch":
+        return main_fscrunch(args)
 
     import torch
 

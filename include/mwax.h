@@ -404,6 +404,25 @@ mwax_status mwax_vis_weights(const uint8_t *d_flags, int32_t n_inputs, int32_t s
 mwax_status mwax_apply_weights(void *d_vis, const float *d_weights, int32_t n_inputs, int32_t n_chan,
                                int32_t n_ints, void *hip_stream);
 
+/* ---- channel averaging (Sec. 2.6) ----
+ *
+ * Average CHAN_TRI visibilities d_vis = [n_ints][n_chan][P] complex64 (DC at
+ * channel n_chan/2) by F = fscrunch into d_out = [n_ints][n_chan/F][P]
+ * complex64, both device memory, not overlapping.  Output channel o is centred
+ * (o - N/2) * F channels from DC (N = n_chan/F, N/2 rounded down) and averages
+ * the channels at offsets d around its centre: for odd F, |d| <= (F-1)/2 at
+ * weight 1; for even F, |d| <= F/2 with the two outermost at weight 1/2, so
+ * that a fine channel on a boundary is shared half and half.  The centre
+ * output channel leaves the DC channel out and is divided by F - 1, every
+ * other by F.  For even N the outermost output channel is the half channel at
+ * the coarse-channel edges (its channels wrap round +-f_s/2) and is meant to be
+ * ignored.  F = 1 copies.  Sums in FP64, one rounding to FP32.  n_inputs
+ * 1..2048, n_chan >= 1, F >= 1 dividing n_chan; n_ints == 0 enqueues nothing.
+ * MWAX_E_INVAL on bad sizes, NULL, misaligned (8 bytes) or overlapping
+ * buffers.  Enqueued on hip_stream (NULL = the null stream); no workspace. */
+mwax_status mwax_fscrunch(const void *d_vis, int32_t n_inputs, int32_t n_chan, int32_t n_ints, int32_t fscrunch,
+                          void *d_out, void *hip_stream);
+
 /* Message for the last error of the calling thread (empty if none). */
 const char *mwax_last_error(void);
 

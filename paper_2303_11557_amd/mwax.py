@@ -31,7 +31,7 @@ EXPORTS = (
     "mwax_batch_set_timing", "mwax_batch_kernel_time", "mwax_batch_sync",
     "mwax_stream_create", "mwax_stream_destroy", "mwax_stream_get_info", "mwax_stream_plan",
     "mwax_stream_now", "mwax_stream_acquire", "mwax_stream_copy_in", "mwax_stream_submit",
-    "mwax_stream_poll", "mwax_stream_vis", "mwax_vis_weights", "mwax_apply_weights",
+    "mwax_stream_poll", "mwax_stream_vis", "mwax_vis_weights", "mwax_apply_weights", "mwax_fscrunch",
 )
 
 
@@ -143,6 +143,7 @@ def lib():
             "mwax_stream_vis": [vp, i32, i64, P(vp)],
             "mwax_vis_weights": [vp, i32, i32, i32, vp, vp],
             "mwax_apply_weights": [vp, vp, i32, i32, i32, vp],
+            "mwax_fscrunch": [vp, i32, i32, i32, i32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -522,6 +523,25 @@ def apply_weights(vis, weights, stream=None):
     _check(lib().mwax_apply_weights(ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
                                     n_in, L, n_ints, ctypes.c_void_p(st.cuda_stream)))
     return vis
+
+
+def fscrunch(vis, F, out=None, stream=None):
+    """Centre-symmetric channel averaging (Sec. 2.6) of CHAN_TRI visibilities
+    [n_ints][L][P] complex64 by F -> [n_ints][L/F][P]."""
+    import torch
+    assert vis.is_cuda and vis.dtype == torch.complex64 and vis.is_contiguous() and vis.dim() == 3
+    n_ints, L, P = vis.shape
+    n_in = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    assert n_in * (n_in + 1) // 2 == P, "P is not a triangular number"
+    F = int(F)
+    assert F >= 1 and L % F == 0, "F must divide the channel count"
+    if out is None:
+        out = torch.empty((n_ints, L // F, P), dtype=torch.complex64, device=vis.device)
+    assert out.is_contiguous() and out.dtype == torch.complex64 and tuple(out.shape) == (n_ints, L // F, P)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().mwax_fscrunch(ctypes.c_void_p(vis.data_ptr()), n_in, L, n_ints, F,
+                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    return out
 
 
 def device_view(ptr, shape, dtype):

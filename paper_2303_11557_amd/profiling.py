@@ -30,6 +30,7 @@ SOURCES = {
     "xengine": os.path.join(HERE, "csrc", "xengine.hip"),
     "pack": os.path.join(HERE, "csrc", "pack.hip"),
     "weights": os.path.join(HERE, "csrc", "weights.hip"),
+    "average": os.path.join(HERE, "csrc", "average.hip"),
 }
 PREC = {"0": "fp32", "1": "fp16", "2": "int8"}
 
@@ -71,6 +72,8 @@ def kernel_key(name):
         return "weights_apply"
     if s.startswith("vis_weights_kernel"):
         return "weights_occupancy"
+    if s.startswith("fscrunch_kernel"):
+        return "average_fscrunch"
     return None
 
 
