@@ -374,7 +374,7 @@ def main_fscrunch(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        n_s = 128                        # pairs of the first 128 inputs: the first 8,256 of the triangle
+        n_s = 256                        # pairs of the first 256 inputs: the first 32,896 of the triangle
         P_s = n_s * (n_s + 1) // 2
         sample = np.ascontiguousarray(vis[:, :, :P_s].cpu().numpy())
         t0, reps = time.perf_counter(), 0

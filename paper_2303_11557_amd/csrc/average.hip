@@ -10,7 +10,7 @@
 // channel is the half channel at the coarse-channel edges: its fine channels
 // wrap round +-f_s/2.  F = 1 copies.
 //
-// One thread per pair and run of 16 consecutive output channels, produced in
+// One thread per pair and run of 4 consecutive output channels, produced in
 // order: for even F the boundary channel a channel shares with the next is
 // kept in a register, so each fine channel is read from HBM once (once more
 // per run).  The sum runs in FP64 in ascending d: the weights are 1 and 1/2,
@@ -26,7 +26,7 @@ namespace mwax {
 namespace {
 
 constexpr int kAvgMaxInputs = 2048;
-constexpr int kSegOut = 16;  // output channels one thread produces in order
+constexpr int kSegOut = 4;   // output channels one thread produces in order
 
 __global__ __launch_bounds__(256) void fscrunch_kernel(const float2 *__restrict__ vis, float2 *__restrict__ out,
                                                        int64_t P, int L, int F, int N, int nseg, int64_t rows,

@@ -42,7 +42,8 @@ def expected(vis_c64, F):
     (3, 16, 16, 1),         # one output channel over the whole band
     (4, 20, 5, 2),          # odd F
     (130, 32, 8, 1),        # ragged pair chunks
-    (3, 40, 2, 1),          # 20 output channels: runs of 16 and 4
+    (3, 40, 2, 1),          # 20 output channels: five runs of 4
+    (3, 44, 4, 1),          # 11 output channels: a ragged last run
     (16, 1024, 8, 2),       # 1024 fine channels to 128
     (512, 128, 4, 1),       # 256 tiles
 ])
