@@ -416,12 +416,16 @@ mwax_status mwax_apply_weights(void *d_vis, const float *d_weights, int32_t n_in
  * output channel leaves the DC channel out and is divided by F - 1, every
  * other by F.  For even N the outermost output channel is the half channel at
  * the coarse-channel edges (its channels wrap round +-f_s/2) and is meant to be
- * ignored.  F = 1 copies.  Sums in FP64, one rounding to FP32.  n_inputs
- * 1..2048, n_chan >= 1, F >= 1 dividing n_chan; n_ints == 0 enqueues nothing.
- * MWAX_E_INVAL on bad sizes, NULL, misaligned (8 bytes) or overlapping
- * buffers.  Enqueued on hip_stream (NULL = the null stream); no workspace. */
-mwax_status mwax_fscrunch(const void *d_vis, int32_t n_inputs, int32_t n_chan, int32_t n_ints, int32_t fscrunch,
-                          void *d_out, void *hip_stream);
+ * ignored.  F = 1 copies.  If d_weights is not NULL ([n_ints][P] float32,
+ * device, as written by mwax_vis_weights) each pair's means are also divided
+ * by its weight where it is positive: the weighting Sec. 2.6 allows during
+ * averaging, in the same pass.  Sums and divisions in FP64, one rounding to
+ * FP32.  n_inputs 1..2048, n_chan >= 1, F >= 1 dividing n_chan; n_ints == 0
+ * enqueues nothing.  MWAX_E_INVAL on bad sizes, NULL, misaligned (8 bytes;
+ * weights 4) or overlapping buffers.  Enqueued on hip_stream (NULL = the null
+ * stream); no workspace. */
+mwax_status mwax_fscrunch(const void *d_vis, const float *d_weights, int32_t n_inputs, int32_t n_chan,
+                          int32_t n_ints, int32_t fscrunch, void *d_out, void *hip_stream);
 
 /* Message for the last error of the calling thread (empty if none). */
 const char *mwax_last_error(void);

@@ -8,7 +8,9 @@
 // The centre output channel leaves the DC channel out and is divided by the
 // weight left (F - 1), every other by F.  With N even the outermost output
 // channel is the half channel at the coarse-channel edges: its fine channels
-// wrap round +-f_s/2.  F = 1 copies.
+// wrap round +-f_s/2.  F = 1 copies.  Optionally each pair's mean is divided by
+// its occupancy weight while averaging (Sec. 2.6 allows a weight here; the
+// weights are those of Sec. 4.1), where the weight is positive.
 //
 // One thread per pair and run of 4 consecutive output channels, produced in
 // order: for even F the boundary channel a channel shares with the next is
@@ -28,7 +30,8 @@ namespace {
 constexpr int kAvgMaxInputs = 2048;
 constexpr int kSegOut = 4;   // output channels one thread produces in order
 
-__global__ __launch_bounds__(256) void fscrunch_kernel(const float2 *__restrict__ vis, float2 *__restrict__ out,
+__global__ __launch_bounds__(256) void fscrunch_kernel(const float2 *__restrict__ vis,
+                                                       const float *__restrict__ weights, float2 *__restrict__ out,
                                                        int64_t P, int L, int F, int N, int nseg, int64_t rows,
                                                        int64_t chunks) {
     const int half = F / 2, oc = N / 2;
@@ -42,6 +45,9 @@ __global__ __launch_bounds__(256) void fscrunch_kernel(const float2 *__restrict_
         const int o0 = (int)(row - j * nseg) * kSegOut;
         const int o1 = min(N, o0 + kSegOut);
         const float2 *vj = vis + j * L * P + p;
+        // occupancy weight of the pair (1 when none is given; 0 leaves the mean)
+        const double wp = weights ? (double)weights[j * P + p] : 1.0;
+        const double scale = wp > 0.0 ? wp : 1.0;
         float2 carry = make_float2(0.0f, 0.0f);
         bool have = false;
         for (int o = o0; o < o1; ++o) {
@@ -68,7 +74,12 @@ __global__ __launch_bounds__(256) void fscrunch_kernel(const float2 *__restrict_
                 }
             }
             const double wsum = centre ? (double)(F - 1) : (double)F;
-            out[(j * N + o) * P + p] = make_float2((float)(re / wsum), (float)(im / wsum));
+            double yr = re / wsum, yi = im / wsum;
+            if (weights) {
+                yr /= scale;
+                yi /= scale;
+            }
+            out[(j * N + o) * P + p] = make_float2((float)yr, (float)yi);
         }
     }
 }
@@ -80,8 +91,8 @@ using namespace mwax;
 
 extern "C" {
 
-mwax_status mwax_fscrunch(const void *d_vis, int32_t n_inputs, int32_t n_chan, int32_t n_ints, int32_t fscrunch,
-                          void *d_out, void *hip_stream) {
+mwax_status mwax_fscrunch(const void *d_vis, const float *d_weights, int32_t n_inputs, int32_t n_chan,
+                          int32_t n_ints, int32_t fscrunch, void *d_out, void *hip_stream) {
     if (n_inputs < 1 || n_inputs > kAvgMaxInputs)
         return fail(MWAX_E_INVAL, "n_inputs must be in 1..%d (got %d)", kAvgMaxInputs, n_inputs);
     if (n_chan < 1) return fail(MWAX_E_INVAL, "n_chan must be >= 1 (got %d)", n_chan);
@@ -92,6 +103,7 @@ mwax_status mwax_fscrunch(const void *d_vis, int32_t n_inputs, int32_t n_chan, i
     if (!d_vis || !d_out) return fail(MWAX_E_INVAL, "null visibility pointer");
     if (((uintptr_t)d_vis & 7) || ((uintptr_t)d_out & 7))
         return fail(MWAX_E_INVAL, "visibilities must be 8-byte aligned");
+    if ((uintptr_t)d_weights & 3) return fail(MWAX_E_INVAL, "weights must be 4-byte aligned");
     const int64_t P = (int64_t)n_inputs * (n_inputs + 1) / 2;
     const int N = n_chan / fscrunch;
     const uintptr_t in0 = (uintptr_t)d_vis, in1 = in0 + (uintptr_t)((int64_t)n_ints * n_chan * P * 8);
@@ -102,7 +114,8 @@ mwax_status mwax_fscrunch(const void *d_vis, int32_t n_inputs, int32_t n_chan, i
     const int64_t chunks = (P + 255) / 256;
     const unsigned grid = (unsigned)std::min<int64_t>(rows * chunks, 1 << 20);
     hipLaunchKernelGGL(fscrunch_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream,
-                       (const float2 *)d_vis, (float2 *)d_out, P, n_chan, fscrunch, N, nseg, rows, chunks);
+                       (const float2 *)d_vis, d_weights, (float2 *)d_out, P, n_chan, fscrunch, N, nseg, rows,
+                       chunks);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "channel averaging launch");
     return ok();

@@ -143,7 +143,7 @@ def lib():
             "mwax_stream_vis": [vp, i32, i64, P(vp)],
             "mwax_vis_weights": [vp, i32, i32, i32, vp, vp],
             "mwax_apply_weights": [vp, vp, i32, i32, i32, vp],
-            "mwax_fscrunch": [vp, i32, i32, i32, i32, vp, vp],
+            "mwax_fscrunch": [vp, vp, i32, i32, i32, i32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -525,9 +525,10 @@ def apply_weights(vis, weights, stream=None):
     return vis
 
 
-def fscrunch(vis, F, out=None, stream=None):
+def fscrunch(vis, F, out=None, stream=None, weights=None):
     """Centre-symmetric channel averaging (Sec. 2.6) of CHAN_TRI visibilities
-    [n_ints][L][P] complex64 by F -> [n_ints][L/F][P]."""
+    [n_ints][L][P] complex64 by F -> [n_ints][L/F][P], optionally divided by the
+    occupancy weights [n_ints][P] (where positive) in the same pass."""
     import torch
     assert vis.is_cuda and vis.dtype == torch.complex64 and vis.is_contiguous() and vis.dim() == 3
     n_ints, L, P = vis.shape
@@ -538,8 +539,12 @@ def fscrunch(vis, F, out=None, stream=None):
     if out is None:
         out = torch.empty((n_ints, L // F, P), dtype=torch.complex64, device=vis.device)
     assert out.is_contiguous() and out.dtype == torch.complex64 and tuple(out.shape) == (n_ints, L // F, P)
+    wp = ctypes.c_void_p()
+    if weights is not None:
+        assert weights.is_contiguous() and weights.dtype == torch.float32 and tuple(weights.shape) == (n_ints, P)
+        wp = ctypes.c_void_p(weights.data_ptr())
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().mwax_fscrunch(ctypes.c_void_p(vis.data_ptr()), n_in, L, n_ints, F,
+    _check(lib().mwax_fscrunch(ctypes.c_void_p(vis.data_ptr()), wp, n_in, L, n_ints, F,
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
     return out
 

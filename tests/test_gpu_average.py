@@ -61,6 +61,26 @@ def test_fscrunch_parity_bit_exact(n_in, L, F, n_ints):
     assert np.array_equal(g.real, re) and np.array_equal(g.imag, im)
 
 
+@pytest.mark.parametrize("n_in,L,F,n_ints", [(130, 32, 8, 2), (7, 20, 5, 1), (512, 128, 4, 1)])
+def test_fscrunch_with_weights_bit_exact(n_in, L, F, n_ints):
+    # weighting during the averaging equals the oracle's average followed by
+    # its normalisation, both in FP64, rounded once
+    log(f"weighted fscrunch n_in={n_in} L={L} F={F} n_ints={n_ints}")
+    P = n_in * (n_in + 1) // 2
+    r = np.random.default_rng(n_in + 5 * L)
+    vis = (r.standard_normal((n_ints, L, P)) + 1j * r.standard_normal((n_ints, L, P))).astype(np.complex64)
+    flags = synth.zero_flags(n_in, 40 * n_ints, 0.3, seed=n_in + 1)
+    flags[0, :40] = 1
+    w = oracle.vis_weights(flags, 40).astype(np.float32)
+    assert np.count_nonzero(w == 0) > 0 and np.count_nonzero((w > 0) & (w < 1)) > 0
+    got = mwax.fscrunch(torch.from_numpy(vis).cuda(), F, weights=torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    want = oracle.apply_weights(oracle.fscrunch(vis.astype(np.complex128), F), w.astype(np.float64))
+    assert np.array_equal(g.real, want.real.astype(np.float32))
+    assert np.array_equal(g.imag, want.imag.astype(np.float32))
+
+
 def test_fscrunch_of_correlator_output():
     # FP32 correlator output averaged on the GPU: bit-exact against the oracle
     # averaging the same output, and within the FP32 path's 1e-5 of the oracle

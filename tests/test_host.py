@@ -215,13 +215,15 @@ def test_weight_arguments_are_checked_without_a_device(lib):
 def test_fscrunch_arguments_are_checked_without_a_device(lib):
     vp = ctypes.c_void_p
     a, b = vp(1 << 20), vp(1 << 30)   # never dereferenced: every call below fails its checks first
-    assert lib.mwax_fscrunch(a, 0, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 0, 1, 1, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 16, 1, 0, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 16, 1, 3, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 16, -1, 4, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(None, 8, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 16, 1, 4, vp((1 << 30) + 4), None) == mwax.MWAX_E_INVAL
-    assert lib.mwax_fscrunch(a, 8, 16, 1, 4, vp((1 << 20) + 64), None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 0, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 0, 1, 1, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 16, 1, 0, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 16, 1, 3, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 16, -1, 4, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(None, None, 8, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 16, 1, 4, vp((1 << 30) + 4), None) == mwax.MWAX_E_INVAL
+    assert lib.mwax_fscrunch(a, None, 8, 16, 1, 4, vp((1 << 20) + 64), None) == mwax.MWAX_E_INVAL
     assert b"overlaps" in lib.mwax_last_error()
-    assert lib.mwax_fscrunch(None, 8, 16, 0, 4, None, None) == mwax.MWAX_OK
+    assert lib.mwax_fscrunch(a, vp((1 << 28) + 2), 8, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
+    assert b"weights" in lib.mwax_last_error()
+    assert lib.mwax_fscrunch(None, None, 8, 16, 0, 4, None, None) == mwax.MWAX_OK
