@@ -227,3 +227,16 @@ def test_fscrunch_arguments_are_checked_without_a_device(lib):
     assert lib.mwax_fscrunch(a, vp((1 << 28) + 2), 8, 16, 1, 4, b, None) == mwax.MWAX_E_INVAL
     assert b"weights" in lib.mwax_last_error()
     assert lib.mwax_fscrunch(None, None, 8, 16, 0, 4, None, None) == mwax.MWAX_OK
+
+
+def test_bench_runs_on_one_gpu_only():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
+    h = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                       capture_output=True, text=True, timeout=120)
+    assert h.returncode == 0
+    for w in ("channel", "batch", "stream", "weights", "fscrunch"):
+        assert w in h.stdout
