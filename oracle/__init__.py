@@ -67,7 +67,7 @@ def _load():
         lib.orc_requantise.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        _c_f32p, _c_i8p]
         lib.orc_calibrate.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                      _c_f64p, _c_f32p, _c_f32p]
+                                      _c_f64p, _c_f32p, _c_f32p, _c_i64p]
         lib.orc_round_fp16.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_double, _c_f64p]
         lib.orc_pack_tilebl.argtypes = [_c_f64p, ctypes.c_int, ctypes.c_int, _c_f64p]
         lib.orc_vis_weights.argtypes = [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
@@ -128,7 +128,8 @@ def dft(x) -> np.ndarray:
 
 
 def fft(x) -> np.ndarray:
-    """Forward radix-2 FFT (recursive decimation in time): complex [L] -> [L]."""
+    """Forward FFT by recursive decimation in time (radix 2 for powers of two,
+    mixed radix on the smallest prime factor otherwise): complex [L] -> [L]."""
     xp = _as_pairs(np.asarray(x, dtype=np.complex128))
     L = xp.shape[0]
     X = np.empty_like(xp)
@@ -199,15 +200,25 @@ def requantise(spec: np.ndarray, inv_s) -> np.ndarray:
     return q
 
 
-def calibrate(spec: np.ndarray):
-    """Per-channel (sigma^2 [L] f64, s [L] f32, inv_s [L] f32) from spectra [M][L][n]."""
+def calibrate(spec: np.ndarray, prev=None, return_populated: bool = False):
+    """Per-channel (sigma^2 [L] f64, s [L] f32, inv_s [L] f32) from spectra [M][L][n].
+
+    Frames (spectrum m of input n) whose L values are all zero are left out of
+    the mean.  If no frame is populated the scales ``prev`` = (s, inv_s) of the
+    previous integration are returned (ones if there is none)."""
     sp = _as_pairs(spec.astype(np.complex128, copy=False))
     M, L, n = sp.shape[:3]
     sig2 = np.empty(L, np.float64)
     s = np.empty(L, np.float32)
     inv = np.empty(L, np.float32)
+    pop = np.zeros(1, np.int64)
     _check(_load().orc_calibrate(_ptr(sp, _c_f64p), M, L, n, _ptr(sig2, _c_f64p),
-                                 _ptr(s, _c_f32p), _ptr(inv, _c_f32p)), "calibrate")
+                                 _ptr(s, _c_f32p), _ptr(inv, _c_f32p), _ptr(pop, _c_i64p)), "calibrate")
+    if pop[0] == 0 and prev is not None:
+        s = np.array(prev[0], np.float32, copy=True)
+        inv = np.array(prev[1], np.float32, copy=True)
+    if return_populated:
+        return sig2, s, inv, int(pop[0])
     return sig2, s, inv
 
 

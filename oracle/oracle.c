@@ -30,8 +30,9 @@
  * Encodings the paper does not have (it computes in FP32 throughout,
  * Sec. 2.5.1 and 3.3) but the precision study needs, written out as rules:
  *   requantise: q = clamp(round_half_even(x * inv_s_c), -127, 127)
- *   calibrate : sigma_c^2 = mean over inputs and spectra of (re^2+im^2)/2,
- *               s_c = 5 sigma_c / 127, inv_s_c = 127 / (5 sigma_c)
+ *   calibrate : sigma_c^2 = mean over the populated (not all-zero) frames
+ *               of (re^2+im^2)/2, s_c = 5 sigma_c / 127, inv_s_c = 127 /
+ *               (5 sigma_c); no populated frame: the previous scales
  *   fp16      : round-half-even to the nearest binary16 value.
  *
  * Parity pins: every function here is pinned by tests against closed forms,
@@ -126,11 +127,58 @@ static void fft_rec(int L, const double *x, int stride, double *X, double *tmp) 
 /* scratch needed by fft_rec for length L: 2L at this level + the child's. */
 static size_t fft_scratch_doubles(int L) { return (size_t)8 * (size_t)(L > 0 ? L : 1) + 8; }
 
+/* ---------------------------------------------------------------------------
+ * The same transform for any L by recursive mixed-radix decimation in time
+ * (the paper's 6,400-point transform, Sec. 2.5.1: 6400 = 2^8 * 5^2).  With p
+ * the smallest prime factor of L and m = L / p, the p interleaved
+ * subsequences x[p n + r] (r < p) are transformed (length m) and combined:
+ *   X[k + m q] = sum_{r<p} W_L^(r (k + m q)) E_r[k],   k < m, q < p,
+ * a direct p-term sum per output.  Powers of two take the radix-2 path above.
+ * ------------------------------------------------------------------------- */
+static int smallest_factor(int L) {
+    for (int p = 2; p * p <= L; ++p)
+        if (L % p == 0) return p;
+    return L;
+}
+
+static void fft_mixed_rec(int L, const double *x, int stride, double *X, double *tmp) {
+    if (L == 1) {
+        X[0] = x[0];
+        X[1] = x[1];
+        return;
+    }
+    const int p = smallest_factor(L), m = L / p;
+    double *E = tmp, *sub = tmp + 2 * L;
+    for (int r = 0; r < p; ++r) fft_mixed_rec(m, x + 2 * (int64_t)stride * r, stride * p, E + 2 * (int64_t)m * r, sub);
+    for (int q = 0; q < p; ++q)
+        for (int k = 0; k < m; ++k) {
+            const int kk = k + m * q;
+            double sr = 0.0, si = 0.0;
+            for (int r = 0; r < p; ++r) {
+                double wr, wi;
+                unit_root((int64_t)r * kk, L, &wr, &wi);
+                const double er = E[2 * ((int64_t)m * r + k)], ei = E[2 * ((int64_t)m * r + k) + 1];
+                sr += er * wr - ei * wi;
+                si += er * wi + ei * wr;
+            }
+            X[2 * kk] = sr;
+            X[2 * kk + 1] = si;
+        }
+}
+
+/* scratch of fft_mixed_rec: 2L at this level + the child's (2L/p + ...) */
+static size_t fft_mixed_scratch_doubles(int L) { return (size_t)4 * (size_t)(L > 0 ? L : 1) + 8; }
+
+static void fft_any(int L, const double *x, double *X, double *tmp) {
+    if (is_pow2(L)) fft_rec(L, x, 1, X, tmp);
+    else fft_mixed_rec(L, x, 1, X, tmp);
+}
+
 int orc_fft(int L, const double *x, double *X) {
-    if (!is_pow2(L)) return ORC_EINVAL;
-    double *tmp = (double *)malloc(sizeof(double) * fft_scratch_doubles(L));
+    if (L < 1) return ORC_EINVAL;
+    double *tmp = (double *)malloc(sizeof(double) * (fft_scratch_doubles(L) + fft_mixed_scratch_doubles(L)));
     if (!tmp) return ORC_ENOMEM;
-    fft_rec(L, x, 1, X, tmp);
+    fft_any(L, x, X, tmp);
     free(tmp);
     return ORC_OK;
 }
@@ -143,15 +191,15 @@ int orc_fft(int L, const double *x, double *X) {
  *   frames: m0 .. m0+nm-1, frame m covers samples mL .. mL+L-1
  *   spec  : [nm][L][n_sel][2] doubles, channel axis fftshifted
  *           (the [time][channel][tile][pol] order of Sec. 2.5.1).
- * use_dft != 0 selects the O(L^2) definition instead of the FFT.
+ * use_dft != 0 selects the O(L^2) definition instead of the FFT (radix-2 for
+ * powers of two, mixed radix otherwise).
  * ------------------------------------------------------------------------- */
 int orc_channelise(const int8_t *volts, int64_t ld, const int32_t *inputs, int n_sel,
                    int64_t m0, int64_t nm, int L, int use_dft, double *spec) {
     if (L < 1 || n_sel < 1 || nm < 0 || m0 < 0) return ORC_EINVAL;
-    if (!use_dft && !is_pow2(L)) return ORC_EINVAL;
     double *x = (double *)malloc(sizeof(double) * 2 * L);
     double *X = (double *)malloc(sizeof(double) * 2 * L);
-    double *tmp = (double *)malloc(sizeof(double) * fft_scratch_doubles(L));
+    double *tmp = (double *)malloc(sizeof(double) * (fft_scratch_doubles(L) + fft_mixed_scratch_doubles(L)));
     if (!x || !X || !tmp) {
         free(x); free(X); free(tmp);
         return ORC_ENOMEM;
@@ -165,7 +213,7 @@ int orc_channelise(const int8_t *volts, int64_t ld, const int32_t *inputs, int n
                 x[2 * q + 1] = (double)fr[2 * q + 1];
             }
             if (use_dft) orc_dft(L, x, X);
-            else fft_rec(L, x, 1, X, tmp);
+            else fft_any(L, x, X, tmp);
             for (int k = 0; k < L; ++k) {
                 int c = (k + L / 2) % L;
                 double *dst = spec + (((m * L) + c) * (int64_t)n_sel + s) * 2;
@@ -320,14 +368,30 @@ int orc_requantise(const double *spec, int64_t M, int L, int n, const float *inv
 /* ---------------------------------------------------------------------------
  * Per-channel scale from the first spectra of an integration (the calibration
  * rule of the int8 requantiser):
- *   sigma2[c] = mean over inputs n and spectra m of (re^2 + im^2) / 2
+ *   a frame (spectrum m of input n) is populated if any of its L channel values
+ *   is nonzero -- a frame of zeroed samples (lost packets are zeroed by the
+ *   capture stage, Sec. 2.4) has an all-zero spectrum and is left out;
+ *   sigma2[c] = sum over populated frames of (re^2 + im^2) / (2 * populated)
  *   s[c]      = 5 sqrt(sigma2) / 127        (clip level 127 <-> 5 sigma)
  *   inv_s[c]  = 127 / (5 sqrt(sigma2))
- * A channel with zero power gets s = inv_s = 1.
+ * A channel with zero power gets s = inv_s = 1.  *populated receives the
+ * count; with none populated sigma2 = 0 and s = inv_s = 1 (the caller keeps
+ * the previous integration's scales then).
  * ------------------------------------------------------------------------- */
 int orc_calibrate(const double *spec, int64_t M, int L, int n, double *sigma2, float *s,
-                  float *inv_s) {
+                  float *inv_s, int64_t *populated) {
     if (M < 1 || L < 1 || n < 1) return ORC_EINVAL;
+    int64_t pop = 0;
+    for (int64_t m = 0; m < M; ++m)
+        for (int64_t k = 0; k < n; ++k) {
+            int any = 0;
+            for (int c = 0; c < L && !any; ++c) {
+                const double *x = spec + ((m * L + c) * n + k) * 2;
+                any = x[0] != 0.0 || x[1] != 0.0;
+            }
+            pop += any;
+        }
+    if (populated) *populated = pop;
     for (int c = 0; c < L; ++c) {
         double acc = 0.0;
         for (int64_t m = 0; m < M; ++m)
@@ -335,7 +399,7 @@ int orc_calibrate(const double *spec, int64_t M, int L, int n, double *sigma2, f
                 const double *x = spec + ((m * L + c) * n + k) * 2;
                 acc += x[0] * x[0] + x[1] * x[1];
             }
-        double v = acc / (2.0 * (double)M * (double)n);
+        double v = pop > 0 ? acc / (2.0 * (double)pop) : 0.0;
         sigma2[c] = v;
         if (v > 0.0) {
             double sd = sqrt(v);

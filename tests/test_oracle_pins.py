@@ -143,9 +143,49 @@ def test_fft_matches_numpy(orc, L):
     assert np.max(np.abs(X - ref)) < 1e-12 * np.max(np.abs(ref)) * math.log2(L)
 
 
-def test_fft_rejects_non_power_of_two(orc):
-    with pytest.raises(ValueError):
-        orc.fft(np.ones(6))
+@pytest.mark.parametrize("L", [3, 5, 6, 10, 20, 25, 50, 100, 400, 1000])
+def test_fft_mixed_radix_matches_dft(orc, L):
+    # lengths with prime factors 2, 3 and 5 take the mixed-radix path
+    x = rng(L).normal(size=L) * 30 + 1j * rng(L + 7).normal(size=L) * 30
+    ref = orc.dft(x)
+    assert np.max(np.abs(orc.fft(x) - ref)) < 1e-12 * np.max(np.abs(ref)) * math.log2(L) * 4
+
+
+def test_fft_6400_matches_numpy_and_parseval(orc):
+    # the F-engine length of Sec. 2.5.1: 6,400 points (2^8 5^2), 200 Hz channels
+    L = 6400
+    x = rng(64).normal(size=L) * 50 + 1j * rng(65).normal(size=L) * 50
+    X = orc.fft(x)
+    ref = np.fft.fft(x)
+    assert np.max(np.abs(X - ref)) < 1e-12 * np.max(np.abs(ref)) * math.log2(L)
+    assert np.sum(np.abs(X) ** 2) == pytest.approx(L * np.sum(np.abs(x) ** 2), rel=1e-12)
+
+
+@pytest.mark.parametrize("k0", [1600, 1, 3199, 4813])
+def test_fft_6400_tone(orc, k0):
+    # exp(+2 pi i k0 q / L) puts L at bin k0 and nothing elsewhere; k0 = L/4 is
+    # the quarter-turn tone i^q, whose samples are exact
+    L = 6400
+    q = np.arange(L)
+    x = np.exp(2j * np.pi * ((k0 * q) % L) / L) if k0 != L // 4 else 1j ** (q % 4)
+    X = orc.fft(x)
+    want = np.zeros(L, complex)
+    want[k0] = L
+    assert np.max(np.abs(X - want)) < 1e-9 * L
+
+
+def test_channelise_6400_against_dft(orc):
+    # two frames of two inputs by the O(L^2) definition; the tone bin k0 = 1600
+    # lands in channel (1600 + 3200) mod 6400 = 4800
+    L = 6400
+    v = rand_volts(2, 2 * L, seed=64)
+    a = orc.channelise(v, L)
+    b = orc.channelise(v, L, use_dft=True)
+    assert np.max(np.abs(a - b)) < 1e-9 * np.max(np.abs(b))
+    t = synth.tone_volts(1, L, L, L // 4, 20, [0])
+    mag = np.abs(orc.channelise(t, L)[0, :, 0])
+    assert int(np.argmax(mag)) == 4800 and mag.max() == pytest.approx(20 * L)
+    assert np.sort(mag)[-2] < 1e-6
 
 
 # ---------------------------------------------------------------------------
@@ -409,6 +449,41 @@ def test_calibrate_white_noise(orc):
     sig2, _, _ = orc.calibrate(orc.channelise(v, L))
     # E|X|^2 = L * 2 * 64.083, so sigma^2 per component = L * 64.083
     assert abs(sig2.mean() / (L * (64 + 1 / 12)) - 1) < 0.02
+
+
+def test_calibrate_leaves_out_zeroed_frames(orc):
+    # Frames of zeroed samples (Sec. 2.4: lost packets are zeroed) have all-zero
+    # spectra; interleaving such frames with the populated ones must leave the
+    # scales bit-for-bit as they were (the sums keep their order, the count its
+    # value).  Dividing by every frame instead would halve sigma^2 here.
+    L, n = 16, 6
+    v = synth.gaussian_volts(n, L * 40, sigma=8.0, seed=77)
+    a = orc.channelise(v, L)
+    b = np.zeros((2 * a.shape[0],) + a.shape[1:], complex)
+    b[0::2] = a
+    sa, s_a, i_a, pa = orc.calibrate(a, return_populated=True)
+    sb, s_b, i_b, pb = orc.calibrate(b, return_populated=True)
+    assert pa == pb == 40 * n
+    assert np.array_equal(sa, sb) and np.array_equal(s_a, s_b) and np.array_equal(i_a, i_b)
+    # zero some whole frames of single inputs: only those drop out of the count
+    z = synth.zero_subblocks(v, np.eye(n, 4, dtype=np.uint8) * 1, 10 * L)  # input k loses frames 10k..10k+9
+    _, _, _, pz = orc.calibrate(orc.channelise(z, L), return_populated=True)
+    assert pz == 40 * n - 4 * 10
+    # a frame with a single nonzero sample counts as populated
+    w = np.zeros((1, 2 * L, 2), np.int8)
+    w[0, 3] = (1, 0)
+    _, _, _, pw = orc.calibrate(orc.channelise(w, L), return_populated=True)
+    assert pw == 1
+
+
+def test_calibrate_empty_window_keeps_previous_scales(orc):
+    spec = np.zeros((5, 8, 3), complex)
+    prev = (np.arange(1, 9, dtype=np.float32), 1 / np.arange(1, 9, dtype=np.float32))
+    sig2, s, inv, pop = orc.calibrate(spec, prev=prev, return_populated=True)
+    assert pop == 0 and np.all(sig2 == 0)
+    assert np.array_equal(s, prev[0]) and np.array_equal(inv, prev[1])
+    _, s1, i1 = orc.calibrate(spec)            # no previous integration: unit scales
+    assert np.all(s1 == 1) and np.all(i1 == 1)
 
 
 def test_round_fp16_matches_numpy(orc):
