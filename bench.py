@@ -60,38 +60,89 @@ def batch_instances():
     return [(BATCH_TILES[i % 3], BATCH_L[(i // 3) % 3], BATCH_TAU[(i // 9) % 3]) for i in range(24)]
 
 
-def cpu_baseline(volts, L, seconds, what):
+def cpu_baseline(volts, L, seconds, what, accuracy=None):
     """The FP64 oracle (channelise + packed-triangle X-engine) timed on the host
     cores over the first spectra of ``volts`` (a device int8 [n][S][2] tensor),
     the sample grown until it takes about ``seconds``; then on one thread over a
-    smaller sample."""
+    smaller sample.  ``accuracy(n_spec, spec, vis)``, if given, receives the
+    oracle's spectra and visibilities of the multi-threaded sample (one
+    integration over its n_spec spectra) and returns the GPU paths' measured
+    error against them, reported under "accuracy"."""
     import oracle
     n_in = volts.shape[0]
     P = n_in * (n_in + 1) // 2
     threads = max(1, min(16, os.cpu_count() or 1))
     max_spec = min(2048, volts.shape[1] // L)
     v_host = volts[:, : max_spec * L].cpu().numpy()
+    kept = {}
 
-    def oracle_rate(n_spec, th):
+    def oracle_rate(n_spec, th, keep=False):
         t0 = time.perf_counter()
         spec = oracle.channelise(v_host, L, nm=n_spec)
-        oracle.correlate(spec, n_spec, threads=th)
-        return time.perf_counter() - t0
+        vis = oracle.correlate(spec, n_spec, threads=th)
+        dt = time.perf_counter() - t0
+        if keep:
+            kept.update(n_spec=n_spec, spec=spec, vis=vis)
+        return dt
 
-    def grow(th, target):
+    def grow(th, target, keep=False):
         n_spec = 2
-        dt = oracle_rate(n_spec, th)
+        dt = oracle_rate(n_spec, th, keep)
         while dt < 0.5 * target and n_spec < max_spec:
             n_spec = int(min(max_spec, max(2 * n_spec, n_spec * target / max(dt, 1e-3))))
-            dt = oracle_rate(n_spec, th)
+            dt = oracle_rate(n_spec, th, keep)
         return n_spec, dt
 
-    n_spec, dt = grow(threads, seconds)
+    n_spec, dt = grow(threads, seconds, keep=accuracy is not None)
+    acc = None
+    if accuracy is not None:
+        acc = accuracy(kept["n_spec"], kept["spec"], kept["vis"])
+        kept.clear()
     n1, dt1 = grow(1, seconds / 3)
-    return {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
-            "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
-                      f"({n_spec * L} samples) of {what}; FP64 FFT + packed triangle; {dt:.1f} s wall",
-            "value_1_thread": P * n1 * L / dt1, "sample_1_thread": f"first {n1} spectra, {dt1:.1f} s wall"}
+    out = {"value": P * n_spec * L / dt, "unit": "CMAC/s", "cores": threads, "kind": "oracle",
+           "sample": f"all {n_in} inputs, all {L} channels, first {n_spec} spectra "
+                     f"({n_spec * L} samples) of {what}; FP64 FFT + packed triangle; {dt:.1f} s wall",
+           "value_1_thread": P * n1 * L / dt1, "sample_1_thread": f"first {n1} spectra, {dt1:.1f} s wall"}
+    if acc is not None:
+        out["accuracy"] = acc
+    return out
+
+
+def gpu_error_vs_oracle(volts, L, n_spec, spec, vis_ref):
+    """Measured error of every X-engine precision against the FP64 oracle on one
+    integration over the first n_spec spectra of the block, all pairs: the
+    largest per-channel relative Frobenius error; for INT8 also the fraction of
+    codes at the clip level +-127 and the codes that differ from the oracle's
+    requantisation of its FP64 spectra (with its own scale calibration)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2303_11557_amd.mwax import Plan, make_config
+    n_in = volts.shape[0]
+    ref = vis_ref[0]
+    den = np.linalg.norm(ref, axis=-1)
+    out = {"integration_spectra": int(n_spec)}
+    for prec in ("int8", "fp16", "fp32"):
+        with Plan(make_config(n_in // 2, L=L, T=n_spec, xprec=prec, max_samples=n_spec * L)) as p:
+            p.channelise(volts[:, : n_spec * L])
+            codes = p.read_channelised().cpu().numpy() if prec == "int8" else None
+            ncal = p.dims.cal_spectra
+            p.correlate()
+            got = p.integrate(1)[0].cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(got - ref, axis=-1) / den
+        ent = {"max_rel_frob_per_channel": float(err.max()), "median_rel_frob_per_channel": float(np.median(err))}
+        if prec == "int8":
+            _, _, inv_o = oracle.calibrate(spec[:ncal])
+            qo = oracle.requantise(spec, inv_o)
+            nd = int(np.count_nonzero(codes != qo))
+            ent.update(codes=int(codes.size), codes_differing_from_fp64_requantisation=nd,
+                       max_code_difference=int(np.abs(codes.astype(np.int16) - qo.astype(np.int16)).max()),
+                       clip_fraction=float(np.count_nonzero(np.abs(codes.astype(np.int16)) == 127) / codes.size))
+            del codes, qo
+        out[prec] = ent
+        torch.cuda.empty_cache()
+    return out
 
 
 def copy_bandwidth():
@@ -628,8 +679,13 @@ def main():
             variants["speedup_vs_fp32_plain"] = round(variants["fp32"]["ms_per_step"] / ms, 2)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same block
-    cpu = None if args.no_cpu_baseline else cpu_baseline(volts, L, args.cpu_seconds,
-                                                         "the same 8 s block")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(
+        volts, L, args.cpu_seconds, "the same 8 s block",
+        accuracy=lambda n, spec, vis: gpu_error_vs_oracle(volts, L, n, spec, vis))
+    if cpu and "accuracy" in cpu:
+        for prec, ent in cpu["accuracy"].items():
+            if prec in variants:
+                variants[prec]["err_vs_fp64"] = ent
 
     rtf = SECONDS / (ms / 1e3)
     line = {
@@ -659,6 +715,7 @@ def main():
         "pack_ms_per_step": round(p_ms / max(args.steps, 1), 4),
         "calibration_ms_per_step": round(c_ms / max(args.steps, 1), 4),
         "variants": variants,
+        "err_vs_fp64": (cpu or {}).get("accuracy", {}).get(args.xprec),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -143,9 +143,13 @@ mwax_status mwax_plan_get_dims(mwax_plan p, mwax_dims *out);
  * to; FP16: to binary16) and writes the channel-major buffer.  For INT8 plans
  * in automatic-scale mode, each integration that begins in this call first
  * has its per-channel scales calibrated from its first cal_spectra spectra
- * (or as many as this call holds): sigma_c^2 = mean of (re^2 + im^2)/2 over
- * inputs and those spectra, s_c = 5 sigma_c / 127, inv_s_c = 127 / (5 sigma_c);
- * a channel with zero power gets s_c = 1.
+ * (or as many as this call holds): sigma_c^2 = sum of (re^2 + im^2) / (2 F)
+ * over the F populated frames (frame m of input n is populated if any of its
+ * L samples is nonzero: the capture stage of Sec. 2.4 zeroes lost packets, and
+ * such frames are left out), s_c = 5 sigma_c / 127, inv_s_c = 127 / (5
+ * sigma_c); a channel with zero power gets s_c = 1.  A window with no
+ * populated frame keeps the scales of the plan's most recent calibrated
+ * integration (1 if there is none; mwax_reset forgets them).
  * Errors: MWAX_E_INVAL (arguments); MWAX_E_STATE if the previous channelised
  * block has not been correlated, or if an integration this call would start
  * needs a device slot still held by a completed integration that
@@ -198,6 +202,15 @@ mwax_status mwax_integrate_raw_i64(mwax_plan p, int64_t *d_vis, float *d_scales,
  * MWAX_E_UNSUPPORTED for other precisions. */
 mwax_status mwax_set_scales(mwax_plan p, const float *h_scales);
 mwax_status mwax_auto_scales(mwax_plan p);
+
+/* INT8 plans: copy the per-channel scales s_c (Sec. 2.5.1 keeps one data path
+ * per fine channel; the requantiser gives each channel its own scale) of the
+ * most recently begun integration into d_scales ([L] float32, device, 4-byte
+ * aligned), enqueued on the plan's stream after that integration's
+ * calibration.  MWAX_E_STATE if no integration has begun since the plan was
+ * created or reset, MWAX_E_UNSUPPORTED for other precisions, MWAX_E_INVAL for
+ * a null or misaligned pointer. */
+mwax_status mwax_get_scales(mwax_plan p, float *d_scales);
 
 /* Discard every integration in progress or not yet emitted and any pending
  * channelised block; the stream position returns to zero. */
@@ -366,14 +379,21 @@ mwax_status mwax_stream_acquire(mwax_stream s, int32_t wait_ms, int32_t *slot, i
 mwax_status mwax_stream_copy_in(mwax_stream s, int32_t slot, const int8_t *h_block, int64_t h_ld);
 /* Submit an acquired buffer as channel's next block (arrival time t_arrival_s
  * on the stream clock).  Enqueues the channel's work after everything enqueued
- * so far on the ingest stream.  MWAX_E_STATE if the slot is not acquired. */
+ * so far on the ingest stream.  MWAX_E_STATE if the slot is not acquired, or
+ * if the block could overwrite an output-ring entry (integration j takes the
+ * entry of j - out_depth) of an integration that mwax_stream_poll has not yet
+ * returned: poll first, or use a deeper ring. */
 mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, double t_arrival_s);
 /* Report finished blocks in submission order (their buffers return to the
  * pool): up to max records into out, count in *n.  wait_ms as in acquire, for
  * at least one record when blocks are in flight. */
 mwax_status mwax_stream_poll(mwax_stream s, int32_t wait_ms, mwax_block_done *out, int32_t max, int32_t *n);
-/* Device pointer of channel's integration j ([L][P] complex64, CHAN_TRI) while
- * it is still in the ring (the out_depth most recent); MWAX_E_STATE if not. */
+/* Device pointer of channel's integration j ([L][P] complex64, CHAN_TRI) once
+ * mwax_stream_poll has returned its block, while it is still in the ring.  The
+ * entry stays unchanged until the caller submits a block for that channel that
+ * reaches it (integration j + out_depth), so reads of it, on any stream, must
+ * be complete before such a submit.  MWAX_E_STATE if j is not (or no longer)
+ * available. */
 mwax_status mwax_stream_vis(mwax_stream s, int32_t channel, int64_t j, void **d_vis);
 
 /* ---- visibility weights (Sec. 4.1; zeroing flags of Sec. 2.4; weight table
@@ -398,9 +418,13 @@ mwax_status mwax_vis_weights(const uint8_t *d_flags, int32_t n_inputs, int32_t s
                              float *d_weights, void *hip_stream);
 /* mwax_apply_weights: normalise CHAN_TRI visibilities in place, d_vis =
  * [n_ints][n_chan][P] complex64, device: V /= w[j][p] (FP32, correctly
- * rounded) where w > 0.  Where w == 0 every product of the sum had a zeroed
- * sample, so V is 0 and is left unchanged.  d_weights as written by
- * mwax_vis_weights.  Sizes as above, n_chan >= 1; d_vis 8-byte aligned. */
+ * rounded) where w > 0; where w == 0, V is left unchanged.  When the sub-block
+ * length is a whole number of FFT frames (Sec. 2.5.1: 64,000-sample blocks of
+ * 6,400-point frames), w == 0 means every product of the sum had a zeroed
+ * sample, so V is 0 there; frames that straddle sub-blocks mix zeroed and live
+ * samples, and V need not vanish (the weight counts sub-blocks, whatever L).
+ * d_weights as written by mwax_vis_weights.  Sizes as above, n_chan >= 1;
+ * d_vis 8-byte aligned. */
 mwax_status mwax_apply_weights(void *d_vis, const float *d_weights, int32_t n_inputs, int32_t n_chan,
                                int32_t n_ints, void *hip_stream);
 

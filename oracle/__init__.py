@@ -74,9 +74,12 @@ def _load():
                                         ctypes.c_int, _c_f64p]
         lib.orc_apply_weights.argtypes = [_c_f64p, _c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.orc_fscrunch.argtypes = [_c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_f64p]
+        lib.orc_delay_correct.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                          _c_f64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_double]
         for f in ("orc_dft", "orc_fft", "orc_channelise", "orc_correlate", "orc_correlate_full",
                   "orc_correlate_i64", "orc_requantise", "orc_calibrate", "orc_round_fp16",
-                  "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights", "orc_fscrunch"):
+                  "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights", "orc_fscrunch",
+                  "orc_delay_correct"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -293,3 +296,18 @@ def fscrunch(vis, F: int) -> np.ndarray:
     out = np.empty((n_ints, L // F, P, 2), np.float64)
     _check(_load().orc_fscrunch(_ptr(vp, _c_f64p), n, L, n_ints, int(F), _ptr(out, _c_f64p)), "fscrunch")
     return _to_complex(out)
+
+
+def delay_correct(spec, delays, step_samples: int, nu_over_fs: float, m0: int = 0) -> np.ndarray:
+    """Fractional delay and phase correction (Sec. 2.5.1, Sec. 4.3) of spectra
+    [M][L][n] (frame m at stream samples (m0 + m) L ..): each sample of input k
+    times exp(-2 pi i ((c - L/2) / L + nu_c / f_s) d) with d = delays[k][step]
+    in samples, step = stream sample // step_samples."""
+    sp = _as_pairs(np.asarray(spec, dtype=np.complex128)).copy()
+    M, L, n = sp.shape[:3]
+    d = np.ascontiguousarray(delays, dtype=np.float64)
+    if d.ndim != 2 or d.shape[0] != n:
+        raise ValueError("delays must be [n_inputs][n_steps]")
+    _check(_load().orc_delay_correct(_ptr(sp, _c_f64p), M, L, n, int(m0), _ptr(d, _c_f64p), d.shape[1],
+                                     int(step_samples), float(nu_over_fs)), "delay_correct")
+    return _to_complex(sp)

@@ -562,3 +562,43 @@ int orc_fscrunch(const double *vis, int n, int L, int n_ints, int F, double *out
             }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Fractional delay and phase correction (Sec. 2.5.1, delay paragraph; Sec.
+ * 4.3).  The capture stage shifts each signal path by whole samples (Sec.
+ * 2.4.1); the residual fractional delay d (in samples, the delay to be applied,
+ * updated every step of step_samples samples: 5 ms in the paper) is applied in
+ * the frequency domain.  Delaying a signal by tau = d / f_s multiplies its
+ * spectrum at sky frequency nu_c + f by exp(-2 pi i (nu_c + f) tau); for the
+ * fftshifted channel c, f = (c - L/2) f_s / L, so every sample of the frame is
+ * multiplied by
+ *   g = exp(-2 pi i (c - L/2) d / L) * exp(-2 pi i (nu_c / f_s) d),
+ * a phase gradient across the channels (its slope set by d alone) times a
+ * phase offset set by the coarse channel's sky frequency nu_c.
+ *   spec   : [M][L][n][2] doubles, corrected in place; spectrum m is the frame
+ *            at stream samples (m0 + m) L .. (m0 + m + 1) L - 1
+ *   delay  : [n][n_steps] samples; step s covers stream samples
+ *            [s step_samples, (s + 1) step_samples) (a whole number of frames)
+ *   nu_over_fs : nu_c / f_s
+ * The phase is reduced to [-1/2, 1/2] revolutions in FP64 before cos/sin.
+ * ------------------------------------------------------------------------- */
+int orc_delay_correct(double *spec, int64_t M, int L, int n, int64_t m0, const double *delay, int64_t n_steps,
+                      int64_t step_samples, double nu_over_fs) {
+    if (M < 0 || L < 1 || n < 1 || m0 < 0 || step_samples < L || step_samples % L) return ORC_EINVAL;
+    for (int64_t m = 0; m < M; ++m) {
+        const int64_t s = (m0 + m) * L / step_samples;
+        if (s >= n_steps) return ORC_EINVAL;
+        for (int c = 0; c < L; ++c)
+            for (int k = 0; k < n; ++k) {
+                const double d = delay[(int64_t)k * n_steps + s];
+                double ph = ((double)(c - L / 2) / (double)L + nu_over_fs) * d;   /* revolutions */
+                ph -= nearbyint(ph);
+                const double gr = cos(2.0 * M_PI * ph), gi = -sin(2.0 * M_PI * ph);
+                double *x = spec + ((m * L + c) * (int64_t)n + k) * 2;
+                const double xr = x[0], xi = x[1];
+                x[0] = xr * gr - xi * gi;
+                x[1] = xr * gi + xi * gr;
+            }
+    }
+    return ORC_OK;
+}

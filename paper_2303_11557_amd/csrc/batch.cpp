@@ -206,7 +206,7 @@ mwax_status layout(mwax_batch b) {
         g.main.max_desc = mdesc;
         g.main.grid = (int)std::min<int64_t>(kMainGridCap, std::max<int64_t>(mitems, mdesc));
         g.stats_off = stats_d;
-        stats_d += (size_t)sdesc * kStatsMaxWG * g.L;
+        stats_d += (size_t)sdesc * kStatsMaxWG * stats_row(g.L);
         for (FTable *t : {&g.stats, &g.main}) {
             t->off_n = off;
             off += 16;
@@ -489,24 +489,26 @@ void build_call(mwax_batch b, const int8_t *const *d_volts, const int64_t *ld_sa
         const int gi = b->group_of[i];
         LGroup &g = b->groups[gi];
         p->segs = segs[i];
+        const size_t chain0 = t.cal.size();   // this instance's calibration descriptors start here
         for (const Segment &s : p->segs) {
             if (s.local0 == 0) {
                 p->slot_owner[s.slot] = s.j;
                 p->slot_count[s.slot] = 0;
+                p->last_slot = s.slot;
                 if (p->xprec == MWAX_X_INT8) {
                     CalDesc cd{};
                     cd.scales = p->scales + (size_t)s.slot * 2 * p->L;
+                    cd.last = p->last;
                     cd.L = p->L;
                     if (p->fixed_mode) {
                         cd.copy_src = p->fixed;
                     } else {
                         FArgs a = calib_args(p, s, d_volts[i], ld_samples[i]);
                         const int nwg = fengine_grid(p->n_in, p->R, a.ngrp, true);
-                        a.stats = b->d_stats + g.stats_off + (size_t)stats_count[gi] * kStatsMaxWG * g.L;
+                        a.stats = b->d_stats + g.stats_off + (size_t)stats_count[gi] * kStatsMaxWG * stats_row(g.L);
                         ++stats_count[gi];
                         cd.stats = a.stats;
                         cd.nwg = nwg;
-                        cd.count = (double)a.nframes * p->n_in;
                         t.fs[gi].push_back(a);
                         const int32_t last = t.fs_b0[gi].empty() ? 0 : t.fs_b0[gi].back();
                         if (t.fs_b0[gi].empty()) t.fs_b0[gi].push_back(0);
@@ -518,6 +520,7 @@ void build_call(mwax_batch b, const int8_t *const *d_volts, const int64_t *ld_sa
             t.fm[gi].push_back(fengine_args(p, s, d_volts[i], ld_samples[i]));
             mwork[gi].push_back((int64_t)s.ngrp * nblk_of(p));
         }
+        if (t.cal.size() > chain0) t.cal[chain0].n_chain = (int32_t)(t.cal.size() - chain0);
     }
     for (size_t gi = 0; gi < ng; ++gi) {
         if (t.fs_b0[gi].empty()) t.fs_b0[gi].push_back(0);
@@ -590,6 +593,9 @@ mwax_status mwax_batch_create(const mwax_config *cfgs, int32_t n, void *hip_stre
         }
         if (cfgs[i].xprec != cfgs[0].xprec)
             return fail(MWAX_E_UNSUPPORTED, "instance %d: every instance of a batch must use the same xprec", i);
+        if (d.fft_len > 1024)
+            return fail(MWAX_E_UNSUPPORTED, "instance %d: batches take FFT lengths up to 1024 (got %d); run the "
+                        "6,400-point transform as a plan", i, d.fft_len);
     }
     if (cfgs[0].xprec == MWAX_X_FP32)
         return fail(MWAX_E_UNSUPPORTED, "FP32 plans run on the vector ALUs and are not batched (use INT8 or FP16)");

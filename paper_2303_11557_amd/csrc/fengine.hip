@@ -16,10 +16,13 @@
 // which is then stored with coalesced 16-byte writes.
 #include <algorithm>
 
+#include "fft_common.h"
 #include "mwax_internal.h"
 
 namespace mwax {
 namespace {
+
+using namespace fft;
 
 // Two-pass split L = L1 * L2 over an FFT group of L2 lanes.  Pass 2 (length L2)
 // is done by each lane on U columns when L2 <= L1.  INT8 at L >= 512 keeps 16
@@ -38,103 +41,6 @@ struct FftShape {
     static constexpr int P = L2 > L1 ? L2 / L1 : 1;
     static constexpr int U = (L2 > 1 && P == 1) ? L1 / L2 : 1;
 };
-
-template <int N>
-__host__ __device__ constexpr int ilog2c() {
-    int l = 0;
-    while ((1 << l) < N) ++l;
-    return l;
-}
-
-template <int N>
-__device__ constexpr int bitrev(int i) {
-    int r = 0;
-    for (int b = 1; b < N; b <<= 1) {
-        r = (r << 1) | (i & 1);
-        i >>= 1;
-    }
-    return r;
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// cos(2 pi e / N) and tan(2 pi e / N) for e < N/2 (N <= 32), rounded to FP32
-// from their FP64 values; the tangent at e = N/4 is unused (that twiddle is -i).
-template <int N>
-struct TwConst;
-template <>
-struct TwConst<2> {
-    static constexpr float c[1] = {1.0f}, t[1] = {0.0f};
-};
-template <>
-struct TwConst<4> {
-    static constexpr float c[2] = {1.0f, 0.0f}, t[2] = {0.0f, 0.0f};
-};
-template <>
-struct TwConst<8> {
-    static constexpr float c[4] = {1.0f, 0.70710677f, 0.0f, -0.70710677f};
-    static constexpr float t[4] = {0.0f, 1.0f, 0.0f, -1.0f};
-};
-template <>
-struct TwConst<16> {
-    static constexpr float c[8] = {1.0f, 0.92387950f, 0.70710677f, 0.38268343f,
-                                   0.0f, -0.38268343f, -0.70710677f, -0.92387950f};
-    static constexpr float t[8] = {0.0f, 0.41421357f, 1.0f, 2.4142137f, 0.0f, -2.4142137f, -1.0f, -0.41421357f};
-};
-template <>
-struct TwConst<32> {
-    static constexpr float c[16] = {1.0f, 0.98078525f, 0.92387950f, 0.83146960f, 0.70710677f, 0.55557024f,
-                                    0.38268343f, 0.19509032f, 0.0f, -0.19509032f, -0.38268343f, -0.55557024f,
-                                    -0.70710677f, -0.83146960f, -0.92387950f, -0.98078525f};
-    static constexpr float t[16] = {0.0f, 0.19891237f, 0.41421357f, 0.66817862f, 1.0f, 1.4966058f,
-                                    2.4142137f, 5.0273395f, 0.0f, -5.0273395f, -2.4142137f, -1.4966058f,
-                                    -1.0f, -0.66817862f, -0.41421357f, -0.19891237f};
-};
-
-// In-register radix-2 decimation-in-time DFT of N points, natural order in and
-// out.  A butterfly a +- W b with W = W_N^e = cos(t) - i sin(t), t = 2 pi e/N:
-// e = 0 and e = N/4 (W = -i) are exact; otherwise W b = cos(t) (b_x + b_y tan(t),
-// b_y - b_x tan(t)), so the pair costs six FMAs (two for the bracket, one per
-// output component) instead of a complex multiply and four additions.
-template <int N>
-__device__ __forceinline__ void dft_regs(float2 *v) {
-    if constexpr (N > 1) {
-        using TC = TwConst<N>;
-        float2 t[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) t[i] = v[bitrev<N>(i)];
-#pragma unroll
-        for (int s = 0; s < ilog2c<N>(); ++s) {
-            const int h = 1 << s;
-#pragma unroll
-            for (int base = 0; base < N; base += 2 * h) {
-#pragma unroll
-                for (int j = 0; j < h; ++j) {
-                    const int e = j * (N / (2 * h));
-                    const float2 a = t[base + j], b = t[base + j + h];
-                    if (e == 0) {
-                        t[base + j] = make_float2(a.x + b.x, a.y + b.y);
-                        t[base + j + h] = make_float2(a.x - b.x, a.y - b.y);
-                    } else if (4 * e == N) {               // W b = (b_y, -b_x)
-                        t[base + j] = make_float2(a.x + b.y, a.y - b.x);
-                        t[base + j + h] = make_float2(a.x - b.y, a.y + b.x);
-                    } else {
-                        const float c = TC::c[e], tn = TC::t[e];
-                        const float u = fmaf(b.y, tn, b.x), w = fmaf(-b.x, tn, b.y);
-                        t[base + j] = make_float2(fmaf(c, u, a.x), fmaf(c, w, a.y));
-                        t[base + j + h] = make_float2(fmaf(-c, u, a.x), fmaf(-c, w, a.y));
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = t[i];
-    }
-}
 
 template <int XP>
 struct PrecTraits;
@@ -212,23 +118,13 @@ struct FCfg {
     static constexpr int OUT_BYTES = L * CP;
     static constexpr int STAGE_BYTES = L2 > 1 ? R * G * SP : 0;
     static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * 8 : 0;
-    static constexpr int RED_BYTES = THREADS * L1 * 4;
+    // statistics pass: per-lane channel sums (L1 floats) and populated-frame counts
+    static constexpr int RED_BYTES = THREADS * (L1 + 1) * 4;
     // load the next item's frames while transforming the current one (where the
     // extra registers keep the occupancy)
     static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && L <= 256;
     static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
 };
-
-// Magic-number rounding: fma(x, s, 1.5 * 2^23) rounds the exact product x * s to
-// the nearest integer, ties to even, and keeps it in the low mantissa bits;
-// clamping to 1.5 * 2^23 +- 127 then leaves the two's-complement int8 code in
-// the low byte.  This is the requantisation rule q = clamp(rne(x s), -127, 127)
-// evaluated on the FP32 spectrum x and FP32 scale s.
-constexpr float kMagic = 12582912.0f;
-__device__ __forceinline__ uint32_t quant8_bits(float x, float s) {
-    const float r = fmaf(x, s, kMagic);
-    return __float_as_uint(fminf(fmaxf(r, kMagic - 127.0f), kMagic + 127.0f));
-}
 
 // One complex int8 sample, converted exactly (one sign-extending byte convert
 // per component).
@@ -277,6 +173,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     float acc[STATS ? L1 : 1];
 #pragma unroll
     for (int i = 0; i < (STATS ? L1 : 1); ++i) acc[i] = 0.0f;
+    int popc = 0;   // statistics pass: populated frames this lane counted
 
     // Staging of the raw frames (two-pass split) through registers; with
     // PREFETCH the global loads of the next item are issued before the current
@@ -370,6 +267,21 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                 const uint8_t *fr = stage + (nl * G + f) * SP;
 #pragma unroll
                 for (int n1 = 0; n1 < L1; ++n1) v[n1] = load_pair(fr + 2 * (r + L2 * n1));
+            }
+            if constexpr (STATS) {
+                // a frame is populated if any of its samples is nonzero (zeroed
+                // frames, from lost packets, are left out of the calibration);
+                // frames past the segment or input range were loaded as zeros
+                bool nz = false;
+#pragma unroll
+                for (int n1 = 0; n1 < L1; ++n1) nz = nz || v[n1].x != 0.0f || v[n1].y != 0.0f;
+                if constexpr (L2 == 1) {
+                    popc += nz ? 1 : 0;
+                } else {
+                    const uint64_t m = __ballot(nz);
+                    const uint64_t gm = L2 == 64 ? m : (m >> (gi * L2)) & ((1ull << (L2 & 63)) - 1ull);
+                    popc += (r == 0 && gm != 0ull) ? 1 : 0;
+                }
             }
             dft_regs<L1>(v);
 
@@ -513,15 +425,24 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         // hold the same channel set; sum them in a fixed order.
         __syncthreads();
         float *red = reinterpret_cast<float *>(smem);   // [THREADS / L2 slots][L2][L1]
+        int *redp = reinterpret_cast<int *>(red + C::THREADS * L1);
 #pragma unroll
         for (int i = 0; i < L1; ++i) red[(gg * L2 + r) * L1 + i] = acc[i];
+        redp[tid] = popc;
         __syncthreads();
         constexpr int NSLOT = C::THREADS / L2;
+        // partial row of this workgroup: L channel sums, then the populated count
+        double *row = a.stats + (int64_t)wg * (L + 1);
         for (int t = tid; t < L; t += C::THREADS) {
             const int rr = t / L1, i = t - rr * L1;
             double sum = 0.0;
             for (int sl = 0; sl < NSLOT; ++sl) sum += (double)red[(sl * L2 + rr) * L1 + i];
-            a.stats[(int64_t)wg * L + chan_of<L, XP>(rr, i)] = sum;
+            row[chan_of<L, XP>(rr, i)] = sum;
+        }
+        if (tid == 0) {
+            int64_t n = 0;
+            for (int t = 0; t < C::THREADS; ++t) n += redp[t];
+            row[L] = (double)n;
         }
     }
 }
@@ -663,56 +584,84 @@ __global__ void twiddle_kernel(float2 *tw, int L) {
     tw[k] = make_float2((float)cs, (float)sn);
 }
 
-// One workgroup per channel: threads sum strided partial rows, then a fixed-order
-// tree in LDS, so the result does not depend on scheduling.
-// Scale of channel c from the partial power sums of nwg workgroups, reduced in a
-// fixed order (bitwise reproducible).
-__device__ void calib_finish_channel(const double *stats, int nwg, int L, double count, float *scales, int c) {
-    __shared__ double part[256];
-    double t = 0.0;
-    for (int w = threadIdx.x; w < nwg; w += 256) t += stats[(int64_t)w * L + c];
+// Scale of channel c from the partial rows of nwg workgroups ([nwg][L + 1]: L
+// power sums, then the populated-frame count), reduced in a fixed order so the
+// result is bitwise reproducible:
+//   sigma^2 = power / (2 populated),  s = 5 sigma / 127,  inv_s = 127 / (5 sigma)
+// (s = inv_s = 1 for a channel of zero power).  With no populated frame the
+// window holds only zeroed samples: the channel keeps last[] (the scales of the
+// plan's most recent calibrated integration).  Otherwise last[] is updated.
+__device__ void calib_finish_channel(const double *stats, int nwg, int L, float *scales, float *last, int c) {
+    __shared__ double part[256], cnt[256];
+    __syncthreads();   // part/cnt of a previous call on this workgroup fully read
+    double t = 0.0, n = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += 256) {
+        t += stats[(int64_t)w * (L + 1) + c];
+        n += stats[(int64_t)w * (L + 1) + L];
+    }
     part[threadIdx.x] = t;
+    cnt[threadIdx.x] = n;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        if ((int)threadIdx.x < h) {
+            part[threadIdx.x] += part[threadIdx.x + h];
+            cnt[threadIdx.x] += cnt[threadIdx.x + h];
+        }
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    const double var = part[0] / (2.0 * count);
-    float s = 1.0f, inv = 1.0f;
-    if (var > 0.0) {
-        const double sd = sqrt(var);
-        s = (float)(5.0 * sd / 127.0);
-        inv = (float)(127.0 / (5.0 * sd));
+    float s = last[c], inv = last[L + c];
+    if (cnt[0] > 0.0) {
+        const double var = part[0] / (2.0 * cnt[0]);
+        s = 1.0f;
+        inv = 1.0f;
+        if (var > 0.0) {
+            const double sd = sqrt(var);
+            s = (float)(5.0 * sd / 127.0);
+            inv = (float)(127.0 / (5.0 * sd));
+        }
+        last[c] = s;
+        last[L + c] = inv;
     }
     scales[c] = s;
     scales[L + c] = inv;
 }
 
-__global__ void calib_finish_kernel(const double *stats, int nwg, int L, double count, float *scales) {
-    calib_finish_channel(stats, nwg, L, count, scales, blockIdx.x);
+__global__ void calib_finish_kernel(const double *stats, int nwg, int L, float *scales, float *last) {
+    calib_finish_channel(stats, nwg, L, scales, last, blockIdx.x);
 }
 
-// One workgroup per (channel, descriptor); descriptors past *ndesc and channels
-// past the descriptor's L return at once.
+// One workgroup per (channel, descriptor).  The descriptors of one instance are
+// consecutive and its first one carries their number (n_chain); that workgroup
+// processes them in order, so an integration whose window holds no populated
+// frame takes the scales of the instance's previous calibrated integration,
+// also within one call.  Other descriptors and channels past L return at once.
 __global__ void calib_batch_kernel(const CalDesc *desc, const int32_t *ndesc) {
     const int d = blockIdx.y, c = blockIdx.x;
     if (d >= *ndesc) return;
-    const CalDesc cd = desc[d];
-    if (c >= cd.L) return;
-    if (cd.copy_src) {
-        if (threadIdx.x == 0) {
-            cd.scales[c] = cd.copy_src[c];
-            cd.scales[cd.L + c] = cd.copy_src[cd.L + c];
+    const CalDesc head = desc[d];
+    if (head.n_chain == 0 || c >= head.L) return;
+    for (int k = 0; k < head.n_chain; ++k) {
+        const CalDesc cd = desc[d + k];
+        if (cd.copy_src) {
+            if (threadIdx.x == 0) {
+                cd.scales[c] = cd.copy_src[c];
+                cd.scales[cd.L + c] = cd.copy_src[cd.L + c];
+            }
+        } else {
+            calib_finish_channel(cd.stats, cd.nwg, cd.L, cd.scales, cd.last, c);
         }
-        return;
     }
-    calib_finish_channel(cd.stats, cd.nwg, cd.L, cd.count, cd.scales, c);
 }
 
 __global__ void copy_scales_kernel(const float *src, float *dst, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
+}
+
+__global__ void fill_f32_kernel(float *dst, float v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
 }
 
 template <int ES>
@@ -829,9 +778,13 @@ hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count, float *scales,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(calib_finish_kernel, dim3(L), dim3(256), 0, s, stats, nwg, L, count, scales);
+hipError_t launch_calib_finish(const double *stats, int nwg, int L, float *scales, float *last, hipStream_t s) {
+    hipLaunchKernelGGL(calib_finish_kernel, dim3(L), dim3(256), 0, s, stats, nwg, L, scales, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *dst, float v, int n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dst, v, n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,361 @@
+// F-engine for the 6,400-point transform of Sec. 2.5.1: every 5 ms frame of
+// 6,400 complex samples of every signal path is transformed into 6,400
+// ultra-fine channels of 200 Hz (unnormalised forward FFT in FP32, channels
+// centre-symmetric with DC at c = 3200, Sec. 2.6), then requantised (INT8 /
+// binary16) or kept (FP32).
+//
+// A workgroup of 256 lanes transforms one frame at a time,
+// 6400 = 25 x 256 = 25 x 16 x 16:
+//   pass 1  lane r holds x[r + 256 n1] (n1 < 25, loaded straight from HBM, the
+//           lanes of a wave reading 128 contiguous bytes per load) and computes
+//           the 25-point DFT in registers as 5 x 5 radix-5 butterflies, then
+//           multiplies bin k1 by W_6400^(r k1);
+//   pass 2  the 25 x 256 block goes through LDS; 400 16-point DFTs over
+//           r = ra + 16 rb (for each k1, ra), times W_256^(ra k2a), in place;
+//   pass 3  400 16-point DFTs over ra (for each k1, k2a), giving bin
+//           k = k1 + 25 k2a + 400 k2b.  Lane d = 25 k2a + k1 holds bins
+//           d + 400 k2b, so the lanes of a wave write 64 consecutive channels.
+// The output is frame-major, [input][frame][channel] (the order a transform
+// produces); corner_turn_kernel then moves it into the channel-major row
+// groups the X-engine reads ([channel][group][input][32 B]): a 6,400-channel
+// row group of one input is 200 KB, beyond the LDS of a workgroup, so the
+// transpose of Sec. 2.5.1 is its own HBM pass at this length.
+#include "fft_common.h"
+#include "mwax_internal.h"
+
+namespace mwax {
+namespace {
+
+using namespace fft;
+
+constexpr int kL = 6400;
+constexpr int kT = 256;          // lanes per workgroup (one frame at a time)
+constexpr int kN1 = 25;          // pass-1 points per lane
+constexpr int kPitch = 273;      // float2 per row of the 25 x 256 exchange block
+                                 // (273 = 17 mod 32 keeps passes 2 and 3 nearly
+                                 // free of bank conflicts)
+constexpr int kNd = 400;         // 16-point DFTs in passes 2 and 3
+
+// cos and sin of 2 pi j / 25 (j < 25), rounded to FP32 from their FP64 values
+struct W25 {
+    static constexpr float c[25] = {
+        1.0f, 0.9685831665992737f, 0.8763066530227661f, 0.728968620300293f, 0.5358268022537231f,
+        0.30901700258255005f, 0.06279052048921585f, -0.187381312251091f, -0.4257792830467224f,
+        -0.6374239921569824f, -0.80901700258255f, -0.9297764897346497f, -0.9921147227287292f,
+        -0.9921147227287292f, -0.9297764897346497f, -0.80901700258255f, -0.6374239921569824f,
+        -0.4257792830467224f, -0.187381312251091f, 0.06279052048921585f, 0.30901700258255005f,
+        0.5358268022537231f, 0.728968620300293f, 0.8763066530227661f, 0.9685831665992737f};
+    static constexpr float s[25] = {
+        0.0f, 0.24868988990783691f, 0.4817536771297455f, 0.6845471262931824f, 0.8443279266357422f,
+        0.9510565400123596f, 0.9980267286300659f, 0.9822872281074524f, 0.9048270583152771f,
+        0.7705132365226746f, 0.5877852439880371f, 0.3681245446205139f, 0.12533323466777802f,
+        -0.12533323466777802f, -0.3681245446205139f, -0.5877852439880371f, -0.7705132365226746f,
+        -0.9048270583152771f, -0.9822872281074524f, -0.9980267286300659f, -0.9510565400123596f,
+        -0.8443279266357422f, -0.6845471262931824f, -0.4817536771297455f, -0.24868988990783691f};
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+// Forward 5-point DFT in place (W = exp(-2 pi i / 5)):
+//   t1 = a1 + a4, t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3
+//   X0 = a0 + t1 + t2
+//   X1, X4 = (a0 + c1 t1 + c2 t2) -+ i (s1 t3 + s2 t4)
+//   X2, X3 = (a0 + c2 t1 + c1 t2) -+ i (s2 t3 - s1 t4)
+// with c_j = cos(2 pi j / 5), s_j = sin(2 pi j / 5).
+__device__ __forceinline__ void radix5(float2 &a0, float2 &a1, float2 &a2, float2 &a3, float2 &a4) {
+    constexpr float c1 = W25::c[5], c2 = W25::c[10], s1 = W25::s[5], s2 = W25::s[10];
+    const float2 t1 = make_float2(a1.x + a4.x, a1.y + a4.y), t2 = make_float2(a2.x + a3.x, a2.y + a3.y);
+    const float2 t3 = make_float2(a1.x - a4.x, a1.y - a4.y), t4 = make_float2(a2.x - a3.x, a2.y - a3.y);
+    const float2 b1 = make_float2(fmaf(c2, t2.x, fmaf(c1, t1.x, a0.x)), fmaf(c2, t2.y, fmaf(c1, t1.y, a0.y)));
+    const float2 b2 = make_float2(fmaf(c1, t2.x, fmaf(c2, t1.x, a0.x)), fmaf(c1, t2.y, fmaf(c2, t1.y, a0.y)));
+    const float2 u = make_float2(fmaf(s2, t4.x, s1 * t3.x), fmaf(s2, t4.y, s1 * t3.y));
+    const float2 w = make_float2(fmaf(-s1, t4.x, s2 * t3.x), fmaf(-s1, t4.y, s2 * t3.y));
+    a0 = make_float2(a0.x + t1.x + t2.x, a0.y + t1.y + t2.y);
+    a1 = make_float2(b1.x + u.y, b1.y - u.x);
+    a4 = make_float2(b1.x - u.y, b1.y + u.x);
+    a2 = make_float2(b2.x + w.y, b2.y - w.x);
+    a3 = make_float2(b2.x - w.y, b2.y + w.x);
+}
+
+// 25-point DFT of v (natural order in and out) as 5 x 5: with n = a + 5 b and
+// k = c + 5 d,  X[c + 5 d] = sum_a W_5^(a d) W_25^(a c) sum_b x[a + 5 b] W_5^(b c).
+__device__ __forceinline__ void dft25(float2 *v) {
+    float2 y[25];   // y[5 a + c]
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        float2 p0 = v[a], p1 = v[a + 5], p2 = v[a + 10], p3 = v[a + 15], p4 = v[a + 20];
+        radix5(p0, p1, p2, p3, p4);
+        y[5 * a] = p0;
+        y[5 * a + 1] = p1;
+        y[5 * a + 2] = p2;
+        y[5 * a + 3] = p3;
+        y[5 * a + 4] = p4;
+    }
+#pragma unroll
+    for (int a = 1; a < 5; ++a)
+#pragma unroll
+        for (int c = 1; c < 5; ++c) y[5 * a + c] = cmul(y[5 * a + c], make_float2(W25::c[a * c], -W25::s[a * c]));
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        float2 q0 = y[c], q1 = y[5 + c], q2 = y[10 + c], q3 = y[15 + c], q4 = y[20 + c];
+        radix5(q0, q1, q2, q3, q4);
+        v[c] = q0;
+        v[c + 5] = q1;
+        v[c + 10] = q2;
+        v[c + 15] = q3;
+        v[c + 20] = q4;
+    }
+}
+
+template <int XP>
+struct Elem;
+template <>
+struct Elem<MWAX_X_INT8> { static constexpr int ES = 1; };
+template <>
+struct Elem<MWAX_X_FP16> { static constexpr int ES = 2; };
+template <>
+struct Elem<MWAX_X_FP32> { static constexpr int ES = 4; };
+
+// Main pass (STATS = false): spectra of frames frame0 .. frame0 + nframes - 1 of
+// every input, written to a.mid[n][frame][channel][re, im].  Statistics pass:
+// per-channel power sums and the populated-frame count of those frames, one
+// row [L + 1] per workgroup in a.stats (see calib_finish_channel).
+template <int XP, bool STATS>
+__global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
+    __shared__ float2 blk[kN1 * kPitch];
+    constexpr int ES = Elem<XP>::ES;
+    const int r = threadIdx.x;
+    const int64_t items = (int64_t)a.n_in * a.nframes;
+
+    // Per-lane twiddles, the same for every frame this lane transforms, kept as
+    // factors: W_6400^(r k1) = W^(r c) W^(5 r d) for k1 = c + 5 d, and
+    // W_256^(ra k) = W_256^(ra e) W_256^(4 ra f) for k = e + 4 f (W = W_6400).
+    float2 p1[5], q1[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        p1[j] = a.tw[(r * j) % kL];
+        q1[j] = a.tw[(5 * r * j) % kL];
+    }
+    const int ra = r & 15;            // pass-2 column of both of this lane's DFTs
+    float2 p2[4], q2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        p2[j] = a.tw[(25 * ra * j) % kL];
+        q2[j] = a.tw[(100 * ra * j) % kL];
+    }
+
+    float acc[STATS ? 32 : 1];
+#pragma unroll
+    for (int i = 0; i < (STATS ? 32 : 1); ++i) acc[i] = 0.0f;
+    int64_t popc = 0;
+
+    // raw samples of an item, x[r + 256 n1] as 16-bit (re, im) words
+    uint32_t raw[kN1];
+    auto fetch = [&](int64_t it) {
+        const int64_t n = it / a.nframes, m = it - n * a.nframes;
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(a.volts + (n * a.ld + (a.frame0 + m) * kL) * 2);
+#pragma unroll
+        for (int n1 = 0; n1 < kN1; ++n1) raw[n1] = src[r + 256 * n1];
+    };
+    if ((int64_t)blockIdx.x < items) fetch(blockIdx.x);
+
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t n = it / a.nframes, m = it - n * a.nframes;
+        float2 v[kN1];
+#pragma unroll
+        for (int n1 = 0; n1 < kN1; ++n1)
+            v[n1] = make_float2((float)(int8_t)raw[n1], (float)(int8_t)(raw[n1] >> 8));
+        if constexpr (STATS) {
+            // a frame is populated if any sample is nonzero (zeroed frames, from
+            // lost packets, are left out of the calibration)
+            bool nz = false;
+#pragma unroll
+            for (int n1 = 0; n1 < kN1; ++n1) nz = nz || (raw[n1] & 0xffffu) != 0u;
+            if (__syncthreads_or(nz ? 1 : 0) && r == 0) ++popc;
+        }
+        if (it + gridDim.x < items) fetch(it + gridDim.x);   // next frame's loads in flight
+
+        // pass 1
+        dft25(v);
+#pragma unroll
+        for (int k1 = 1; k1 < kN1; ++k1) {
+            if (k1 % 5) v[k1] = cmul(v[k1], p1[k1 % 5]);
+            if (k1 / 5) v[k1] = cmul(v[k1], q1[k1 / 5]);
+        }
+        __syncthreads();   // the previous frame's pass 3 has read blk
+#pragma unroll
+        for (int k1 = 0; k1 < kN1; ++k1) blk[k1 * kPitch + r] = v[k1];
+        __syncthreads();
+
+        // pass 2: DFTs d = 16 k1 + ra over rb, in place
+        for (int d = r; d < kNd; d += kT) {
+            float2 *col = blk + (d >> 4) * kPitch + ra;
+            float2 w[16];
+#pragma unroll
+            for (int rb = 0; rb < 16; ++rb) w[rb] = col[16 * rb];
+            dft_regs<16>(w);
+#pragma unroll
+            for (int k = 1; k < 16; ++k) {
+                if (k % 4) w[k] = cmul(w[k], p2[k % 4]);
+                if (k / 4) w[k] = cmul(w[k], q2[k / 4]);
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) col[16 * k] = w[k];
+        }
+        __syncthreads();
+
+        // pass 3: DFTs d = 25 k2a + k1 over ra; bins d + 400 k2b
+#pragma unroll
+        for (int slot = 0; slot < 2; ++slot) {
+            const int d = r + slot * kT;
+            if (d < kNd) {
+                const int k1 = d % kN1, k2a = d / kN1;
+                const float2 *row = blk + k1 * kPitch + 16 * k2a;
+                float2 z[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) z[q] = row[q];
+                dft_regs<16>(z);
+#pragma unroll
+                for (int k2b = 0; k2b < 16; ++k2b) {
+                    const float2 X = z[k2b];
+                    if constexpr (STATS) {
+                        acc[slot * 16 + k2b] += X.x * X.x + X.y * X.y;
+                    } else {
+                        const int c = (d + 400 * k2b + kL / 2) % kL;
+                        uint8_t *dst = a.mid + (((n * a.mid_frames) + a.frame0 + m) * kL + c) * 2 * ES;
+                        if constexpr (XP == MWAX_X_INT8) {
+                            const float s = a.inv_s[c];
+                            const uint32_t br = quant8_bits(X.x, s) & 0xffu, bi = quant8_bits(X.y, s) & 0xffu;
+                            *reinterpret_cast<uint16_t *>(dst) = (uint16_t)(br | (bi << 8));
+                        } else if constexpr (XP == MWAX_X_FP16) {
+                            const _Float16 hr = (_Float16)(X.x * a.half_scale), hi = (_Float16)(X.y * a.half_scale);
+                            *reinterpret_cast<uint32_t *>(dst) = (uint32_t)__builtin_bit_cast(uint16_t, hr) |
+                                                                 ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+                        } else {
+                            *reinterpret_cast<float2 *>(dst) = X;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (STATS) {
+        // every channel belongs to exactly one (lane, slot, k2b) of the workgroup
+        double *row = a.stats + (int64_t)blockIdx.x * (kL + 1);
+#pragma unroll
+        for (int slot = 0; slot < 2; ++slot) {
+            const int d = r + slot * kT;
+            if (d < kNd) {
+#pragma unroll
+                for (int k2b = 0; k2b < 16; ++k2b) row[(d + 400 * k2b + kL / 2) % kL] = (double)acc[slot * 16 + k2b];
+            }
+        }
+        if (r == 0) row[kL] = (double)popc;
+    }
+}
+
+// Frame-major spectra [input][frame][channel][re, im] (elements of ES bytes) ->
+// channel-major row groups [channel][group][input][32 B] (the row layout of
+// row_re_off / row_im_gap).  A workgroup moves one tile of G frames (one row
+// group) x 64 channels x 16 inputs = 32 KB through LDS: 16-byte loads along the
+// channel axis, 16-byte stores of whole half rows, 512 contiguous bytes per
+// channel.  Frames past the segment and inputs past n_in read as zeros; rows of
+// inputs past n_in are not written.
+template <int ES>
+__global__ __launch_bounds__(256) void corner_turn_kernel(CornerArgs a) {
+    constexpr int G = 16 / ES, CB = 64, NB = 16;
+    constexpr int UPF = CB * 2 * ES / 16;           // 16-byte units per (input, frame)
+    constexpr int CPU = 16 / (2 * ES);              // channels per unit
+    __shared__ __align__(16) uint8_t img[CB * NB * kRowBytes];
+    const int g = blockIdx.x, c0 = blockIdx.y * CB, n0 = blockIdx.z * NB;
+    const int tid = threadIdx.x;
+    const int fvalid = (int)min((int64_t)G, a.nframes - (int64_t)g * G);
+#pragma unroll
+    for (int j = 0; j < NB * G * UPF / 256; ++j) {
+        const int u = tid + 256 * j;
+        const int nl = u / (G * UPF), rem = u - nl * (G * UPF);
+        const int f = rem / UPF, cu = rem - f * UPF;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (n0 + nl < a.n_in && f < fvalid)
+            val = *reinterpret_cast<const uint4 *>(
+                a.mid + (((int64_t)(n0 + nl) * a.mid_frames + a.frame0 + (int64_t)g * G + f) * a.L + c0) * 2 * ES +
+                cu * 16);
+        const uint8_t *b = reinterpret_cast<const uint8_t *>(&val);
+        const int re = row_re_off(f, ES), im = re + row_im_gap(ES);
+#pragma unroll
+        for (int e = 0; e < CPU; ++e) {
+            uint8_t *row = img + ((cu * CPU + e) * NB + nl) * kRowBytes;
+            if constexpr (ES == 1) {
+                row[re] = b[2 * e];
+                row[im] = b[2 * e + 1];
+            } else if constexpr (ES == 2) {
+                *reinterpret_cast<uint16_t *>(row + re) = *reinterpret_cast<const uint16_t *>(b + 4 * e);
+                *reinterpret_cast<uint16_t *>(row + im) = *reinterpret_cast<const uint16_t *>(b + 4 * e + 2);
+            } else {
+                *reinterpret_cast<uint32_t *>(row + re) = *reinterpret_cast<const uint32_t *>(b + 8 * e);
+                *reinterpret_cast<uint32_t *>(row + im) = *reinterpret_cast<const uint32_t *>(b + 8 * e + 4);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CB * NB * 2 / 256; ++j) {
+        const int v = tid + 256 * j;
+        const int cl = v / (NB * 2), rem = v - cl * (NB * 2);
+        const int nl = rem >> 1, h = rem & 1;
+        if (n0 + nl < a.n_in) {
+            const uint4 val = *reinterpret_cast<const uint4 *>(img + (cl * NB + nl) * kRowBytes + h * 16);
+            *reinterpret_cast<uint4 *>(a.chan + ((((int64_t)(c0 + cl) * a.NG + a.grp0 + g) * a.n_in) + n0 + nl) *
+                                                    kRowBytes + h * 16) = val;
+        }
+    }
+}
+
+template <int XP>
+hipError_t launch_fft_xp(const FArgs &a, bool stats, int grid, hipStream_t s) {
+    if (stats) hipLaunchKernelGGL((fft6400_kernel<XP, true>), dim3((unsigned)grid), dim3(kT), 0, s, a);
+    else hipLaunchKernelGGL((fft6400_kernel<XP, false>), dim3((unsigned)grid), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int fft6400_grid(int n_in, int64_t nframes, bool stats) {
+    const int64_t items = (int64_t)n_in * nframes;
+    const int64_t cap = stats ? kStatsMaxWG : 8192;
+    return (int)(items < cap ? items : cap);
+}
+
+int fft6400_lds_bytes() { return kN1 * kPitch * 8; }
+
+hipError_t launch_fft6400(int xprec, const FArgs &a, hipStream_t s) {
+    const bool stats = a.stats_mode != 0;
+    const int grid = fft6400_grid(a.n_in, a.nframes, stats);
+    if (grid < 1) return hipSuccess;
+    switch (xprec) {
+        case MWAX_X_INT8: return launch_fft_xp<MWAX_X_INT8>(a, stats, grid, s);
+        case MWAX_X_FP16: return launch_fft_xp<MWAX_X_FP16>(a, stats, grid, s);
+        case MWAX_X_FP32: return launch_fft_xp<MWAX_X_FP32>(a, stats, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_corner_turn(int esize, const CornerArgs &a, hipStream_t s) {
+    const int64_t G = 16 / esize;
+    const int64_t ngrp = (a.nframes + G - 1) / G;
+    if (ngrp < 1) return hipSuccess;
+    if (a.L % 64 != 0 || ngrp > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)ngrp, (unsigned)(a.L / 64), (unsigned)((a.n_in + 15) / 16));
+    switch (esize) {
+        case 1: hipLaunchKernelGGL(corner_turn_kernel<1>, grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(corner_turn_kernel<2>, grid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(corner_turn_kernel<4>, grid, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mwax

@@ -68,7 +68,10 @@ struct FArgs {
     const float2 *tw;       // W_L^k = exp(-2 pi i k / L), k < L
     const float *inv_s;     // [L] INT8 inverse scales of the segment's integration
     float half_scale;       // 2^-e for FP16
-    double *stats;          // stats mode: [n_workgroups][L] partial power sums
+    double *stats;          // stats mode: [n_workgroups][L + 1] partial power sums
+                            // per channel, then the count of populated frames
+    uint8_t *mid;           // L = 6400: frame-major spectra [N_in][mid_frames][L][2]
+    int64_t mid_frames;     // frames per input row of mid
 };
 
 constexpr int kStatsMaxWG = 1024;   // calibration partial rows per launch (max)
@@ -78,10 +81,33 @@ constexpr int kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 int fengine_pick_R(int L, int xprec, int n_in, int lds_limit);
 hipError_t launch_fengine(int L, int xprec, const FArgs &a, hipStream_t s);
 hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s);
-// stats: [nwg][L] partial sums -> scales [2][L] (s, inv_s) for one slot
-hipError_t launch_calib_finish(const double *stats, int nwg, int L, double count, float *scales,
-                               hipStream_t s);
+// Rows of the statistics buffer: L channel sums + the populated-frame count.
+inline int64_t stats_row(int L) { return (int64_t)L + 1; }
+// stats: [nwg][L + 1] partial sums -> scales [2][L] (s, inv_s) for one slot; a
+// window without populated frames takes last [2][L] (the most recent calibrated
+// scales), which every other calibration updates
+hipError_t launch_calib_finish(const double *stats, int nwg, int L, float *scales, float *last, hipStream_t s);
 hipError_t launch_copy_scales(const float *src, float *dst, int L, hipStream_t s);
+hipError_t launch_fill_f32(float *dst, float v, int n, hipStream_t s);
+
+// The 6,400-point transform of Sec. 2.5.1 (fft6400.hip): a frame-major main
+// pass into FArgs::mid, then the corner-turn into the channel-major buffer.
+constexpr int kUltraFineL = 6400;
+struct CornerArgs {
+    const uint8_t *mid;     // [N_in][mid_frames][L][2] elements
+    int64_t mid_frames;
+    int64_t frame0;         // first frame of the segment in mid
+    int64_t nframes;        // frames of the segment
+    uint8_t *chan;          // channel-major buffer [L][NG][N_in][32 B]
+    int64_t NG;
+    int64_t grp0;           // first destination group of the segment
+    int32_t n_in;
+    int32_t L;
+};
+int fft6400_grid(int n_in, int64_t nframes, bool stats);
+int fft6400_lds_bytes();
+hipError_t launch_fft6400(int xprec, const FArgs &a, hipStream_t s);
+hipError_t launch_corner_turn(int esize, const CornerArgs &a, hipStream_t s);
 
 // Reads a workgroup-uniform table entry through the constant address space: the
 // compiler may then reload its fields where they are used (as it does for kernel
@@ -107,12 +133,15 @@ hipError_t fengine_prepare_batch(int L, int xprec);   // LDS attribute, once, ou
 // Batched scale calibration finish (or copy of fixed scales), one descriptor per
 // integration that begins in the call.
 struct CalDesc {
-    const double *stats;    // [nwg][L] partial power sums (NULL in copy mode)
+    const double *stats;    // [nwg][L + 1] partial power sums and counts (NULL in copy mode)
     const float *copy_src;  // copy mode: [2][L] scales to install
     float *scales;          // [2][L] destination (s, inv_s)
-    double count;           // inputs x spectra of the calibration window
+    float *last;            // [2][L] the instance's most recent calibrated scales
     int32_t nwg;
     int32_t L;
+    int32_t n_chain;        // first descriptor of an instance: its descriptors in
+                            // this call (consecutive, processed in order); else 0
+    int32_t pad;
 };
 hipError_t launch_calib_batch(const CalDesc *desc, const int32_t *ndesc, int max_desc, int max_L, hipStream_t s);
 

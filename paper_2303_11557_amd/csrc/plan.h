@@ -45,8 +45,11 @@ struct mwax_plan_s {
     float *scales = nullptr;        // [nslots][2][L] (s, inv_s)
     float *fixed = nullptr;         // [2][L] user scales
     float *ones = nullptr;          // [2][L] = 1
+    float *last = nullptr;          // [2][L] scales of the most recent calibrated integration
+    int last_slot = -1;             // slot of the most recently begun integration
     float2 *tw = nullptr;
-    double *stats = nullptr;        // [kStatsMaxWG][L]
+    double *stats = nullptr;        // [kStatsMaxWG][L + 1]
+    uint8_t *mid = nullptr;         // L = 6400: frame-major spectra of a call [n_in][max_spectra][L][2]
 
     int64_t g_chan = 0;             // stream spectra channelised (incl. the pending block)
     bool pending = false;           // a channelised block awaits mwax_correlate
@@ -57,6 +60,7 @@ struct mwax_plan_s {
     int64_t next_emit = 0;
     bool fixed_mode = false;
     bool in_batch = false;          // owned by a batch or stream (destroyed with it)
+    bool static_ws = false;         // workspace lives in the library's static device array
     // Clear a slot's integrators when its integration is emitted.  Off only where
     // every integration's first X-engine flush overwrites the whole slot
     // (whole-segment INT8/FP16 work of a batch); mwax_correlate clears a slot
@@ -110,6 +114,11 @@ mwax_status plan_segments(mwax_plan p, int64_t M, std::vector<Segment> &out);
 FArgs calib_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld);
 // F-engine main-pass launch arguments of a segment.
 FArgs fengine_args(mwax_plan p, const Segment &s, const int8_t *volts, int64_t ld);
+// Statistics-pass workgroups of a calibration launch (rows of its partial sums).
+int stats_grid(mwax_plan p, const FArgs &a);
+// The F-engine main pass of one segment: the fused single-kernel transform, or
+// for L = 6400 the frame-major transform followed by the corner-turn.
+hipError_t launch_fengine_segment(mwax_plan p, const Segment &s, const FArgs &a);
 // X-engine launch arguments of a segment.
 XArgs xengine_args(mwax_plan p, const Segment &s);
 

@@ -66,8 +66,8 @@ mwax_status mwax::derive(const mwax_config *cfg, mwax_dims *o) {
     const int64_t L = llround(lf);
     if (L < 1 || std::fabs(lf - (double)L) > 1e-9 * lf)
         return fail(MWAX_E_INVAL, "coarse_bw/fine_chan = %.9g is not a whole number of channels", lf);
-    if (!is_pow2(L) || L > 1024)
-        return fail(MWAX_E_UNSUPPORTED, "FFT length %lld: only powers of two 1..1024 are implemented",
+    if ((!is_pow2(L) || L > 1024) && L != kUltraFineL)
+        return fail(MWAX_E_UNSUPPORTED, "FFT length %lld: powers of two 1..1024 and 6400 are implemented",
                     (long long)L);
     if (!(cfg->int_time_s > 0) || !std::isfinite(cfg->int_time_s))
         return fail(MWAX_E_INVAL, "int_time_s must be positive");
@@ -97,8 +97,10 @@ mwax_status mwax::derive(const mwax_config *cfg, mwax_dims *o) {
     const int64_t NG = (o->max_spectra + o->group - 1) / o->group + segs;
     const uint64_t chan_b = (uint64_t)L * NG * n_in * kRowBytes;
     const uint64_t integ_b = (uint64_t)o->n_slots * integ_slot_bytes(cfg->xprec, T, L, o->n_pairs);
-    const uint64_t small_b = (uint64_t)o->n_slots * 2 * L * 4 + 4 * L * 4 + L * 8 + (uint64_t)kStatsMaxWG * L * 8;
-    o->workspace_bytes = chan_b + integ_b + small_b;
+    const uint64_t small_b = (uint64_t)o->n_slots * 2 * L * 4 + 6 * L * 4 + L * 8 + (uint64_t)kStatsMaxWG * (L + 1) * 8;
+    const uint64_t esize = cfg->xprec == MWAX_X_INT8 ? 1 : (cfg->xprec == MWAX_X_FP16 ? 2 : 4);
+    const uint64_t mid_b = L == kUltraFineL ? (uint64_t)n_in * cfg->max_samples * 2 * esize : 0;
+    o->workspace_bytes = chan_b + integ_b + small_b + mid_b;
     o->sample_time_s = 1.0 / cfg->coarse_bw_hz;
     o->fine_chan_hz = cfg->coarse_bw_hz / (double)L;
     o->int_time_s = (double)T * (double)L / cfg->coarse_bw_hz;
@@ -114,13 +116,17 @@ void mwax::free_plan(mwax_plan p) {
         (void)hipEventDestroy(e.b);
     }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    (void)hipFree(p->chan);
-    (void)hipFree(p->integ);
-    (void)hipFree(p->scales);
-    (void)hipFree(p->fixed);
-    (void)hipFree(p->ones);
-    (void)hipFree(p->tw);
-    (void)hipFree(p->stats);
+    if (!p->static_ws) {
+        (void)hipFree(p->chan);
+        (void)hipFree(p->integ);
+        (void)hipFree(p->scales);
+        (void)hipFree(p->fixed);
+        (void)hipFree(p->ones);
+        (void)hipFree(p->last);
+        (void)hipFree(p->tw);
+        (void)hipFree(p->stats);
+        (void)hipFree(p->mid);
+    }
     delete p;
 }
 
@@ -189,7 +195,30 @@ FArgs mwax::fengine_args(mwax_plan p, const Segment &s, const int8_t *volts, int
     a.tw = p->tw;
     a.inv_s = p->scales + (size_t)s.slot * 2 * p->L + p->L;
     a.half_scale = std::ldexp(1.0f, -fp16_exponent(p->L));
+    a.mid = p->mid;
+    a.mid_frames = p->d.max_spectra;
     return a;
+}
+
+int mwax::stats_grid(mwax_plan p, const FArgs &a) {
+    return p->L == kUltraFineL ? fft6400_grid(p->n_in, a.nframes, true) : fengine_grid(p->n_in, p->R, a.ngrp, true);
+}
+
+hipError_t mwax::launch_fengine_segment(mwax_plan p, const Segment &s, const FArgs &a) {
+    if (p->L != kUltraFineL) return launch_fengine(p->L, p->xprec, a, p->stream);
+    hipError_t e = launch_fft6400(p->xprec, a, p->stream);
+    if (e != hipSuccess) return e;
+    CornerArgs c{};
+    c.mid = p->mid;
+    c.mid_frames = p->d.max_spectra;
+    c.frame0 = s.frame0;
+    c.nframes = s.nframes;
+    c.chan = p->chan;
+    c.NG = p->NG;
+    c.grp0 = s.grp0;
+    c.n_in = p->n_in;
+    c.L = p->L;
+    return launch_corner_turn(p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4), c, p->stream);
 }
 
 XArgs mwax::xengine_args(mwax_plan p, const Segment &s) {
@@ -218,6 +247,7 @@ mwax_status begin_integrations(mwax_plan p, const int8_t *volts, int64_t ld, boo
         if (s.local0 != 0) continue;
         p->slot_owner[s.slot] = s.j;
         p->slot_count[s.slot] = 0;
+        p->last_slot = s.slot;
         if (p->xprec != MWAX_X_INT8) continue;
         float *dst = p->scales + (size_t)s.slot * 2 * p->L;
         hipError_t e;
@@ -225,12 +255,13 @@ mwax_status begin_integrations(mwax_plan p, const int8_t *volts, int64_t ld, boo
             e = launch_copy_scales(p->fixed_mode ? p->fixed : p->ones, dst, 2 * p->L, p->stream);
         } else {
             const FArgs a = calib_args(p, s, volts, ld);
-            e = timed(p, 3, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
+            e = timed(p, 3, [&] {
+                return p->L == kUltraFineL ? launch_fft6400(p->xprec, a, p->stream)
+                                           : launch_fengine(p->L, p->xprec, a, p->stream);
+            });
             if (e == hipSuccess) {
-                const int nwg = fengine_grid(p->n_in, p->R, a.ngrp, true);
-                e = timed(p, 3, [&] {
-                    return launch_calib_finish(p->stats, nwg, p->L, (double)a.nframes * p->n_in, dst, p->stream);
-                });
+                const int nwg = stats_grid(p, a);
+                e = timed(p, 3, [&] { return launch_calib_finish(p->stats, nwg, p->L, dst, p->last, p->stream); });
             }
         }
         if (e != hipSuccess) return hip_fail(e, "scale calibration launch");
@@ -254,7 +285,13 @@ mwax_status mwax_plan_derive(const mwax_config *cfg, mwax_dims *out) {
     return s == MWAX_OK ? ok() : s;
 }
 
-mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out) {
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Create a plan whose workspace is allocated with hipMalloc (ws == NULL) or
+// carved out of ws[0 .. cap) (no allocation; MWAX_E_INVAL if it does not fit).
+mwax_status create_plan(const mwax_config *cfg, void *hip_stream, mwax_plan *out, uint8_t *ws, size_t cap) {
     if (!out) return fail(MWAX_E_INVAL, "null output handle");
     *out = nullptr;
     mwax_dims d;
@@ -279,9 +316,10 @@ mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan
         lds_limit <= 0)
         lds_limit = 65536;
     if (lds_limit > kMaxLds) lds_limit = kMaxLds;
-    p->R = fengine_pick_R(p->L, p->xprec, p->n_in, lds_limit);
-    if (fengine_lds_bytes(p->L, p->xprec, p->R, false) > lds_limit ||
-        fengine_lds_bytes(p->L, p->xprec, p->R, true) > lds_limit) {
+    p->R = p->L == kUltraFineL ? 1 : fengine_pick_R(p->L, p->xprec, p->n_in, lds_limit);
+    if (p->L == kUltraFineL ? fft6400_lds_bytes() > lds_limit
+                            : (fengine_lds_bytes(p->L, p->xprec, p->R, false) > lds_limit ||
+                               fengine_lds_bytes(p->L, p->xprec, p->R, true) > lds_limit)) {
         mwax_status r = fail(MWAX_E_UNSUPPORTED, "F-engine for L = %d needs %d bytes of LDS, device allows %d",
                              p->L, fengine_lds_bytes(p->L, p->xprec, p->R, false), lds_limit);
         delete p;
@@ -296,36 +334,63 @@ mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan
     p->slot_owner.assign(p->nslots, -1);
     p->slot_count.assign(p->nslots, 0);
 
+    // workspace buffers, in order
+    const size_t esize = p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4);
+    void **ptrs[] = {(void **)&p->chan, &p->integ, (void **)&p->scales, (void **)&p->fixed, (void **)&p->ones,
+                     (void **)&p->last, (void **)&p->tw, (void **)&p->stats, (void **)&p->mid};
+    const size_t sizes[] = {(size_t)p->L * p->NG * p->n_in * kRowBytes, p->slot_bytes * p->nslots,
+                            (size_t)p->nslots * 2 * p->L * sizeof(float), (size_t)2 * p->L * sizeof(float),
+                            (size_t)2 * p->L * sizeof(float), (size_t)2 * p->L * sizeof(float),
+                            (size_t)p->L * sizeof(float2), (size_t)kStatsMaxWG * stats_row(p->L) * sizeof(double),
+                            p->L == kUltraFineL ? (size_t)p->n_in * d.max_spectra * p->L * 2 * esize : 0};
+    constexpr int nbuf = (int)(sizeof(sizes) / sizeof(sizes[0]));
     hipError_t e = hipSuccess;
-    auto alloc = [&](void **ptr, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(ptr, bytes);
-    };
-    alloc((void **)&p->chan, (size_t)p->L * p->NG * p->n_in * kRowBytes);
-    alloc(&p->integ, p->slot_bytes * p->nslots);
-    alloc((void **)&p->scales, (size_t)p->nslots * 2 * p->L * sizeof(float));
-    alloc((void **)&p->fixed, (size_t)2 * p->L * sizeof(float));
-    alloc((void **)&p->ones, (size_t)2 * p->L * sizeof(float));
-    alloc((void **)&p->tw, (size_t)p->L * sizeof(float2));
-    alloc((void **)&p->stats, (size_t)kStatsMaxWG * p->L * sizeof(double));
-    if (e != hipSuccess) {
-        mwax_status r = hip_fail(e, "workspace allocation");
-        free_plan(p);
-        return r;
+    if (ws) {
+        size_t total = 0;
+        for (int k = 0; k < nbuf; ++k) total += align256(sizes[k]);
+        if (total > cap) {
+            mwax_status r = fail(MWAX_E_INVAL, "plan workspace of %zu bytes exceeds the %zu-byte static workspace",
+                                 total, cap);
+            delete p;
+            return r;
+        }
+        size_t off = 0;
+        for (int k = 0; k < nbuf; ++k) {
+            *ptrs[k] = sizes[k] > 0 ? ws + off : nullptr;
+            off += align256(sizes[k]);
+        }
+        p->static_ws = true;
+    } else {
+        for (int k = 0; k < nbuf && e == hipSuccess; ++k)
+            if (sizes[k] > 0) e = hipMalloc(ptrs[k], sizes[k]);
+        if (e != hipSuccess) {
+            mwax_status r = hip_fail(e, "workspace allocation");
+            free_plan(p);
+            return r;
+        }
     }
-    std::vector<float> ones(2 * p->L, 1.0f);
-    e = hipMemcpyAsync(p->ones, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->fixed, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice, p->stream);
+    // initial state, written by kernels on the plan's stream
+    e = launch_fill_f32(p->ones, 1.0f, 2 * p->L, p->stream);
+    if (e == hipSuccess) e = launch_fill_f32(p->fixed, 1.0f, 2 * p->L, p->stream);
     if (e == hipSuccess) e = launch_twiddles(p->tw, p->L, p->stream);
     if (e == hipSuccess) e = launch_fill_zero(p->integ, p->slot_bytes * p->nslots, p->stream);
     if (e == hipSuccess) e = launch_copy_scales(p->ones, p->scales, 2 * p->L, p->stream);
+    if (e == hipSuccess) e = launch_copy_scales(p->ones, p->last, 2 * p->L, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         mwax_status r = hip_fail(e, "plan initialisation");
-        free_plan(p);
+        if (p->static_ws) delete p;   // nothing allocated
+        else free_plan(p);
         return r;
     }
     *out = p;
     return ok();
+}
+
+}  // namespace
+
+mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out) {
+    return create_plan(cfg, hip_stream, out, nullptr, 0);
 }
 
 mwax_status mwax_plan_destroy(mwax_plan p) {
@@ -360,7 +425,7 @@ mwax_status mwax_channelise(mwax_plan p, const int8_t *d_volts, int64_t n_sample
     if (st != MWAX_OK) return st;
     for (const Segment &s : p->segs) {
         const FArgs a = fengine_args(p, s, d_volts, ld_samples);
-        hipError_t e = timed(p, 0, [&] { return launch_fengine(p->L, p->xprec, a, p->stream); });
+        hipError_t e = timed(p, 0, [&] { return launch_fengine_segment(p, s, a); });
         if (e != hipSuccess) return hip_fail(e, "F-engine launch");
     }
     p->pending = true;
@@ -535,6 +600,16 @@ mwax_status mwax_set_scales(mwax_plan p, const float *h_scales) {
     return ok();
 }
 
+mwax_status mwax_get_scales(mwax_plan p, float *d_scales) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "scales exist for INT8 plans only");
+    if (!d_scales || ((uintptr_t)d_scales & 3) != 0) return fail(MWAX_E_INVAL, "null or misaligned output");
+    if (p->last_slot < 0) return fail(MWAX_E_STATE, "no integration has begun");
+    hipError_t e = launch_copy_scales(p->scales + (size_t)p->last_slot * 2 * p->L, d_scales, p->L, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "scale copy");
+    return ok();
+}
+
 mwax_status mwax_auto_scales(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "scales exist for INT8 plans only");
@@ -546,7 +621,9 @@ mwax_status mwax_auto_scales(mwax_plan p) {
 mwax_status mwax_reset(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     hipError_t e = launch_fill_zero(p->integ, p->slot_bytes * p->nslots, p->stream);
+    if (e == hipSuccess) e = launch_copy_scales(p->ones, p->last, 2 * p->L, p->stream);
     if (e != hipSuccess) return hip_fail(e, "reset");
+    p->last_slot = -1;
     std::fill(p->slot_owner.begin(), p->slot_owner.end(), -1);
     std::fill(p->slot_count.begin(), p->slot_count.end(), 0);
     p->g_chan = 0;

@@ -48,6 +48,7 @@ struct mwax_stream_s {
     hipStream_t lanes[kLanes] = {};
     std::vector<mwax_plan> plans;
     std::vector<int64_t> blocks_seen;       // per channel
+    std::vector<int64_t> reported_end;      // per channel: integrations [0, end) returned by poll
     int n_in = 0, L = 0;
     int64_t P = 0;
     uint64_t block_bytes = 0;
@@ -214,6 +215,7 @@ mwax_status mwax_stream_create(const mwax_stream_config *cfg, mwax_stream *out) 
         s->device_bytes += rb;
     }
     s->blocks_seen.assign(cfg->n_channels, 0);
+    s->reported_end.assign(cfg->n_channels, 0);
     for (uint64_t k = 0; k < slots; ++k) {
         void *b = nullptr;
         e = hipMalloc(&b, block_bytes);
@@ -317,6 +319,19 @@ mwax_status mwax_stream_submit(mwax_stream s, int32_t slot, int32_t channel, dou
     if (max_new > s->cfg.out_depth)
         return fail(MWAX_E_INVAL, "a block can complete %lld integrations; out_depth is %d", (long long)max_new,
                     s->cfg.out_depth);
+    // Back-pressure on the output ring: integration j overwrites the entry of
+    // j - out_depth.  Every entry this block overwrites must belong to an
+    // integration that poll has already returned (the caller has been told it
+    // is ready, and its reads of it come before this submit).  The block
+    // completes integrations next_emit .. end_int - 1 (every earlier completed
+    // one has been emitted: the lane emits after each call).
+    const int64_t end_int = (p->g_chan + s->cfg.block_samples / s->L) / p->T;
+    const int64_t newest_victim = end_int - 1 - s->cfg.out_depth;
+    if (newest_victim >= 0 && newest_victim >= s->reported_end[channel])
+        return fail(MWAX_E_STATE,
+                    "channel %d: this block could overwrite integration %lld in the output ring, which "
+                    "mwax_stream_poll has not returned yet (poll first, or raise out_depth)",
+                    channel, (long long)newest_victim);
     hipEvent_t done = stream_event(s);
     if (!done) return fail(MWAX_E_NOMEM, "event creation");
     hipEvent_t join = stream_event(s);
@@ -395,7 +410,10 @@ mwax_status mwax_stream_poll(mwax_stream s, int32_t wait_ms, mwax_block_done *ou
         pend.push_back(rec);
     }
     const int32_t k = std::min<int32_t>(max, (int32_t)pend.size());
-    for (int32_t i = 0; i < k; ++i) out[i] = pend[i];
+    for (int32_t i = 0; i < k; ++i) {
+        out[i] = pend[i];
+        s->reported_end[pend[i].channel] = pend[i].first_int + pend[i].n_ints;
+    }
     pend.erase(pend.begin(), pend.begin() + k);
     *n = k;
     return ok();
@@ -405,8 +423,9 @@ mwax_status mwax_stream_vis(mwax_stream s, int32_t channel, int64_t j, void **d_
     if (!s || !d_vis) return fail(MWAX_E_INVAL, "null argument");
     if (channel < 0 || channel >= s->cfg.n_channels) return fail(MWAX_E_INVAL, "channel %d out of range", channel);
     mwax_plan p = s->plans[channel];
-    if (j < 0 || j >= p->next_emit || j < p->next_emit - s->cfg.out_depth)
-        return fail(MWAX_E_STATE, "integration %lld of channel %d is not in the output ring", (long long)j, channel);
+    if (j < 0 || j >= s->reported_end[channel] || j < p->next_emit - s->cfg.out_depth)
+        return fail(MWAX_E_STATE, "integration %lld of channel %d is not in the output ring (not yet returned "
+                    "by mwax_stream_poll, or overwritten)", (long long)j, channel);
     *d_vis = (uint8_t *)s->ring[channel] + (size_t)(j % s->cfg.out_depth) * s->L * s->P * 8;
     return ok();
 }

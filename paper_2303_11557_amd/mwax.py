@@ -24,7 +24,7 @@ _ORDER = {"tri": ORDER_CHAN_TRI, "tile_bl": ORDER_TILE_BL}
 EXPORTS = (
     "mwax_plan_derive", "mwax_plan_create", "mwax_plan_destroy", "mwax_plan_get_dims",
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
-    "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales",
+    "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
@@ -116,6 +116,7 @@ def lib():
             "mwax_integrate_raw_i64": [vp, vp, vp, i32, P(i32)],
             "mwax_set_scales": [vp, P(ctypes.c_float)],
             "mwax_auto_scales": [vp],
+            "mwax_get_scales": [vp, vp],
             "mwax_reset": [vp],
             "mwax_sync": [vp],
             "mwax_set_timing": [vp, i32],
@@ -298,6 +299,15 @@ class Plan:
 
     def auto_scales(self):
         _check(lib().mwax_auto_scales(self.h))
+
+    def get_scales(self, out=None):
+        """INT8 plans: the scales s_c [L] float32 of the most recently begun integration."""
+        t = self.torch
+        if out is None:
+            out = t.empty((self.L,), dtype=t.float32, device="cuda")
+        assert out.is_cuda and out.dtype == t.float32 and out.is_contiguous() and out.numel() >= self.L
+        _check(lib().mwax_get_scales(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def reset(self):
         _check(lib().mwax_reset(self.h))
@@ -504,6 +514,7 @@ def vis_weights(flags, subs_per_int, out=None, stream=None):
     if out is None:
         out = torch.empty((n_ints, n_in * (n_in + 1) // 2), dtype=torch.float32, device=flags.device)
     assert out.is_contiguous() and out.dtype == torch.float32 and out.numel() >= n_ints * (n_in * (n_in + 1) // 2)
+    assert out.is_cuda and out.device == flags.device, "out must be on the flags' device"
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().mwax_vis_weights(ctypes.c_void_p(flags.data_ptr()), n_in, subs, n_ints,
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
@@ -519,6 +530,7 @@ def apply_weights(vis, weights, stream=None):
     n_in = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
     assert n_in * (n_in + 1) // 2 == P, "P is not a triangular number"
     assert weights.is_contiguous() and weights.dtype == torch.float32 and tuple(weights.shape) == (n_ints, P)
+    assert weights.is_cuda and weights.device == vis.device, "weights must be on the visibilities' device"
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().mwax_apply_weights(ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
                                     n_in, L, n_ints, ctypes.c_void_p(st.cuda_stream)))
@@ -539,9 +551,11 @@ def fscrunch(vis, F, out=None, stream=None, weights=None):
     if out is None:
         out = torch.empty((n_ints, L // F, P), dtype=torch.complex64, device=vis.device)
     assert out.is_contiguous() and out.dtype == torch.complex64 and tuple(out.shape) == (n_ints, L // F, P)
+    assert out.is_cuda and out.device == vis.device, "out must be on the visibilities' device"
     wp = ctypes.c_void_p()
     if weights is not None:
         assert weights.is_contiguous() and weights.dtype == torch.float32 and tuple(weights.shape) == (n_ints, P)
+        assert weights.is_cuda and weights.device == vis.device, "weights must be on the visibilities' device"
         wp = ctypes.c_void_p(weights.data_ptr())
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().mwax_fscrunch(ctypes.c_void_p(vis.data_ptr()), wp, n_in, L, n_ints, F,

@@ -107,7 +107,7 @@ def test_batch_full_shape_sampled():
     torch.cuda.synchronize()
     log("batch full shape: voltages made")
     check = {2: [1], 5: [1], 8: [0, 1]}     # 256 tiles, tau = 0.5 s, L = 32 / 128 / 1024
-    sel = [0, 1, 2, 130, 257, 400, 511]
+    sel = [0, 1, 2, 100, 130, 200, 257, 330, 400, 460, 511]   # both column halves of every tile
     cols = torch.tensor(pair_cols(sel), device="cuda")
     host = {i: volts[i].cpu().numpy() for i in check}
     sel_t = torch.tensor(sel, device="cuda")
@@ -145,11 +145,16 @@ def test_stream_full_shape_sampled():
     n_in = 2 * n_tiles
     T = int(round(tau * F_S / L))
     cfg = make_config(n_tiles, L=L, int_time_s=tau, xprec="int8", max_samples=call)
-    sel = [0, 1, 5, 130, 300, 511]
+    sel = [0, 1, 5, 100, 130, 200, 300, 330, 460, 511]   # both column halves of every tile
     cols = torch.tensor(pair_cols(sel), device="cuda")
     with Stream(cfg, 2, block, 2 * n_in * block * 2, out_depth=6) as s:
         host = None
+        recs = []
         for b, ch in ((0, 0), (0, 1), (1, 0)):
+            if (b, ch) == (1, 0):
+                # channel 0's second block reuses ring entries of its first: poll that first
+                while not any(r["channel"] == 0 for r in recs):
+                    recs += s.poll(-1)
             slot, ptr = s.acquire(-1)
             view = device_view(ptr, (n_in, block, 2), torch.int8)
             synth.device_volts(view, seed=synth.MWAX_SEED + 4 + ch, L=L, s0=b * block,
@@ -158,7 +163,6 @@ def test_stream_full_shape_sampled():
                 torch.cuda.synchronize()
                 host = view.cpu().numpy()       # 10.5 GB: the calibration needs every input
             s.submit(slot, ch, s.now())
-        recs = []
         while len(recs) < 3:
             recs += s.poll(-1)
         log(f"stream full shape: blocks done, latencies {[round(r['t_ready_s'] - r['t_arrival_s'], 3) for r in recs]}")

@@ -146,3 +146,49 @@ def test_stream_device_producer_and_fp16():
         ref = reference(whole, prec)
         log(f"device producer {prec}: {len(recs)} blocks")
         assert np.array_equal(got, ref)
+
+
+def test_stream_output_ring_back_pressure():
+    # A ring of two blocks' integrations: block b overwrites the entries of block
+    # b - 2, so its submit is refused until poll has returned block b - 2; block
+    # b - 1's visibilities are read after poll returns it, while block b runs on
+    # the lane.  Everything read equals the plan driven alone.
+    hv = host_volts(0)
+    budget = 3 * (2 * N_TILES) * BLOCK * 2
+    P = 2 * N_TILES * (2 * N_TILES + 1) // 2
+    got = {}
+    with Stream(cfg(), 1, BLOCK, budget, out_depth=4) as s:
+        seen = []
+
+        def wait_block(k):
+            while not any(r["block"] == k for r in seen):
+                seen.extend(s.poll(-1))
+
+        def read(j):
+            got[j] = device_view(s.vis_ptr(0, j), (L, P), torch.complex64).clone()
+
+        for b in range(N_BLOCKS):
+            slot, _ = s.acquire(wait_ms=-1)
+            s.copy_in(slot, hv[:, b * BLOCK:(b + 1) * BLOCK])
+            if b == 2:
+                with pytest.raises(mwax.MwaxError) as e:
+                    s.submit(slot, 0, s.now())            # block 0 not returned by poll yet
+                assert e.value.status == mwax.MWAX_E_STATE and "poll" in str(e.value)
+            if b >= 2:
+                wait_block(b - 2)
+            s.submit(slot, 0, s.now())
+            if b >= 1:
+                wait_block(b - 1)                          # block b may still be running
+                read(2 * b - 2)
+                read(2 * b - 1)
+                torch.cuda.synchronize()
+        wait_block(N_BLOCKS - 1)
+        read(2 * N_BLOCKS - 2)
+        read(2 * N_BLOCKS - 1)
+        torch.cuda.synchronize()
+        with pytest.raises(mwax.MwaxError) as e:
+            s.vis_ptr(0, 2 * N_BLOCKS - 5)                 # overwritten by the last block
+        assert e.value.status == mwax.MWAX_E_STATE
+    ref = reference(hv.cuda())
+    assert sorted(got) == list(range(2 * N_BLOCKS))
+    assert np.array_equal(torch.stack([got[j] for j in range(2 * N_BLOCKS)]).cpu().numpy(), ref)

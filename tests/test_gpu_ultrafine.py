@@ -1,0 +1,175 @@
+"""GPU parity of the 6,400-point F-engine (Sec. 2.5.1: 5 ms frames of 6,400
+samples -> 200 Hz ultra-fine channels) and of the averaging of its visibilities
+(Sec. 2.6), against the FP64 oracle (whose mixed-radix FFT is pinned against
+the O(L^2) DFT).  Bounds as in test_gpu_parity: FP32 spectra within
+2e-6 log2(L) of the rms, int8 codes and binary16 values equal to the oracle's
+rounding of its FP64 spectra except next to a rounding boundary, FP32
+visibilities within 1e-5 (relative Frobenius per channel), INT8 sums bit-exact
+against the integer oracle on the GPU's codes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2303_11557_amd import mwax  # noqa: E402
+from paper_2303_11557_amd.mwax import Plan, make_config  # noqa: E402
+
+L = 6400
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    mwax.lib()
+    yield
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel_frob(got, ref):
+    return np.linalg.norm(got - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def test_fft6400_fp32_spectra():
+    n_tiles, M = 3, 21                   # 21 frames: ragged against the 4-frame rows
+    v = synth.gaussian_volts(2 * n_tiles, L * M, seed=640, sources=[synth.Source(3.0, 77)], L=L)
+    with Plan(make_config(n_tiles, L=L, T=M, xprec="fp32", max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        got = p.read_channelised().cpu().numpy().astype(np.float64)
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = oracle.channelise(v, L)
+    assert got.shape == ref.shape == (M, L, 2 * n_tiles)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    err = np.max(np.abs(got - ref)) / rms
+    log(f"fft6400 fp32: max error {err:.3g} of rms")
+    assert err < 2e-6 * math.log2(L)
+
+
+def test_fft6400_tone_lands_in_closed_form_channel():
+    # the quarter-turn tone i^q: exact samples, all power in bin 1600 = channel 4800
+    M = 5
+    v = synth.tone_volts(4, L * M, L, L // 4, 20, [0, 1, 2, 3])
+    with Plan(make_config(2, L=L, T=M, xprec="fp32", max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        got = p.read_channelised().cpu().numpy()
+    mag = np.abs(got[..., 0] + 1j * got[..., 1])
+    assert np.allclose(mag[:, 4800, :], 20 * L, rtol=1e-6)
+    assert np.delete(mag, 4800, axis=1).max() < 1e-4 * 20 * L
+
+
+def test_fft6400_int8_fixed_scales():
+    n_tiles, M = 2, 18
+    v = synth.gaussian_volts(2 * n_tiles, L * M, seed=641, sources=[synth.Source(3.0, -1234)], L=L)
+    ref = oracle.channelise(v, L)
+    s = (5.0 * np.sqrt(L * 64.0) / 127.0 * (1.0 + 0.01 * np.arange(L) / L)).astype(np.float32)
+    inv = (np.float32(1.0) / s).astype(np.float32)
+    with Plan(make_config(n_tiles, L=L, T=M, xprec="int8", max_samples=L * M)) as p:
+        p.set_scales(s)
+        p.channelise(torch.from_numpy(v).cuda())
+        q = p.read_channelised().cpu().numpy().astype(np.int64)
+    qo = oracle.requantise(ref, inv).astype(np.int64)
+    diff = q != qo
+    xs = np.stack([ref.real, ref.imag], -1) * inv[None, :, None, None].astype(np.float64)
+    frac = np.abs(np.abs(xs - np.floor(xs)) - 0.5)
+    log(f"fft6400 int8: {np.count_nonzero(diff)} of {diff.size} codes differ from the FP64 requantisation")
+    assert np.all(np.abs(q - qo)[diff] == 1)
+    assert np.all(frac[diff] < 1e-3 * math.log2(L) / 7.0)
+    assert diff.mean() <= 1e-4
+    assert q.min() >= -127 and q.max() <= 127
+
+
+def test_fft6400_fp16_rounding():
+    n_tiles, M = 2, 10
+    v = synth.gaussian_volts(2 * n_tiles, L * M, seed=642)
+    ref = oracle.channelise(v, L)
+    e = (int(math.ceil(math.log2(L))) + 1) // 2
+    with Plan(make_config(n_tiles, L=L, T=M, xprec="fp16", max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        h = p.read_channelised().cpu().numpy().astype(np.float64)
+    x = np.stack([ref.real, ref.imag], -1) * 2.0 ** -e
+    fft_err = 2e-6 * math.log2(L) * np.sqrt(np.mean(np.abs(ref) ** 2)) * 2.0 ** -e
+    half_ulp = np.maximum(2.0 ** (np.floor(np.log2(np.maximum(np.abs(h), 2.0 ** -14))) - 11), 2.0 ** -25)
+    assert np.all(np.abs(h - x) <= half_ulp * 1.0001 + fft_err)
+    want = np.stack([oracle.round_fp16(ref.real, 2.0 ** -e), oracle.round_fp16(ref.imag, 2.0 ** -e)], -1)
+    assert (h != want).mean() < 1e-2
+
+
+def run_plan(v, n_tiles, T, prec, chunks, max_ints=8):
+    outs = []
+    d = torch.from_numpy(v).cuda()
+    with Plan(make_config(n_tiles, L=L, T=T, xprec=prec, max_samples=max(chunks))) as p:
+        s0 = 0
+        for n in chunks:
+            p.channelise(d[:, s0:s0 + n])
+            p.correlate()
+            s0 += n
+            outs.append(p.integrate(max_ints).clone())
+        torch.cuda.synchronize()
+    return torch.cat(outs).cpu().numpy().astype(np.complex128)
+
+
+def test_fft6400_fp32_end_to_end_and_fscrunch():
+    # 3 tiles, integrations of 12 frames (60 ms), calls crossing them; then the
+    # averaging of the paper's three output widths (fscrunch 200, 50, 5)
+    n_tiles, T = 3, 12
+    S = 2 * T * L
+    v = synth.gaussian_volts(2 * n_tiles, S, seed=643, sources=[synth.Source(4.0, 900)], L=L)
+    ref = oracle.fx_correlate(v, L, T, threads=8)
+    got = run_plan(v, n_tiles, T, "fp32", [5 * L, 14 * L, 5 * L])
+    assert got.shape == ref.shape == (2, L, 21)
+    err = rel_frob(got, ref)
+    log(f"fft6400 fp32 end to end: max per-channel rel-Frobenius {err.max():.3g}")
+    assert err.max() <= 1e-5
+    d_vis = torch.from_numpy(got.astype(np.complex64)).cuda()
+    for F in (200, 50, 5):
+        avg = mwax.fscrunch(d_vis, F).cpu().numpy().astype(np.complex128)
+        want = oracle.fscrunch(ref, F)
+        e = rel_frob(avg, want)
+        log(f"fscrunch {F}: {avg.shape[1]} channels, max rel-Frobenius {e.max():.3g}")
+        assert avg.shape == (2, L // F, 21) and e.max() <= 1e-5
+
+
+def test_fft6400_int8_end_to_end():
+    # automatic scales from the first 21 frames of each integration; int64 sums
+    # bit-exact against the integer oracle on the GPU's codes
+    n_tiles, T = 4, 30
+    S = T * L
+    v = synth.gaussian_volts(2 * n_tiles, S, seed=644, sources=[synth.Source(3.0, -2000)], L=L)
+    with Plan(make_config(n_tiles, L=L, T=T, xprec="int8", max_samples=S)) as p:
+        ncal = p.dims.cal_spectra
+        assert ncal == 21
+        p.channelise(torch.from_numpy(v).cuda())
+        q = p.read_channelised().cpu().numpy()
+        p.correlate()
+        raw, sc = p.integrate_raw(1)
+        raw, sc = raw.cpu().numpy(), sc.cpu().numpy()
+    assert raw.shape == (1, L, 36, 2)
+    assert np.array_equal(raw, oracle.correlate_i64(q, T))
+    spec = oracle.channelise(v, L)
+    _, s_o, inv_o = oracle.calibrate(spec[:ncal])
+    assert np.max(np.abs(sc[0] / s_o - 1)) < 1e-5
+    qo = oracle.requantise(spec, inv_o)
+    d = q.astype(np.int32) - qo.astype(np.int32)
+    assert np.abs(d).max() <= 1 and np.count_nonzero(d) <= 1e-4 * d.size
+    ref = oracle.correlate(spec, T)
+    got = (raw[..., 0] + 1j * raw[..., 1]) * (sc.astype(np.float64) ** 2)[:, :, None]
+    err = rel_frob(got, ref)
+    log(f"fft6400 int8 end to end: max per-channel rel-Frobenius vs FP64 {err.max():.3g}")
+    assert err.max() < 3e-3
+
+
+def test_fft6400_rejected_by_batches():
+    with pytest.raises(mwax.MwaxError) as e:
+        mwax.Batch([make_config(2, L=L, T=10, xprec="int8", max_samples=10 * L)])
+    assert e.value.status == mwax.MWAX_E_UNSUPPORTED

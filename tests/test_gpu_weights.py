@@ -124,3 +124,103 @@ def test_weights_end_to_end_fp32():
         assert np.all(got[j][:, w_orc[j] == 0] == 0)
     assert np.count_nonzero(w_orc == 0) > 0
     assert np.count_nonzero((w_orc > 0) & (w_orc < 1)) > 0
+
+
+def test_weights_end_to_end_int8_zeroed_calibration():
+    """INT8 with zeroed sub-blocks inside the calibration windows.  Zeroed frames
+    are left out of the scale calibration, and a window with none populated
+    keeps the previous integration's scales, as the oracle defines; the int64
+    sums equal the oracle's integer X-engine on the GPU's codes, the codes agree
+    with the oracle's requantisation of its FP64 spectra, few codes clip, and the
+    normalised result matches the oracle's chain."""
+    n_tiles, L, sub_len, subs, J = 8, 16, 256, 10, 3
+    n_in = 2 * n_tiles
+    T = subs * sub_len // L                   # 160 spectra: the whole integration calibrates
+    S = J * subs * sub_len
+    flags = synth.zero_flags(n_in, J * subs, 0.2, seed=12)
+    flags[:, subs:2 * subs] = 1               # integration 1: every input zeroed throughout
+    flags[:, 2 * subs + 1:3 * subs] = 1       # integration 2: only its first sub-block is live
+    v = synth.zero_subblocks(synth.gaussian_volts(n_in, S, seed=synth.MWAX_SEED + 6,
+                                                  sources=[synth.Source(3.0, 5)], L=L), flags, sub_len)
+    d = torch.from_numpy(v).cuda()
+    with Plan(make_config(n_tiles, L=L, T=T, xprec="int8", max_samples=S)) as p:
+        ncal = p.dims.cal_spectra
+        assert ncal == T
+        p.channelise(d)
+        q = p.read_channelised().cpu().numpy()
+        p.correlate()
+        raw, sc = p.integrate_raw(J)
+        p.reset()
+        p.channelise(d)
+        p.correlate()
+        vis = p.integrate(J).clone()
+        w = mwax.vis_weights(torch.from_numpy(flags).cuda(), subs)
+        mwax.apply_weights(vis, w)
+        torch.cuda.synchronize()
+    raw, sc = raw.cpu().numpy(), sc.cpu().numpy()
+    assert raw.shape[0] == J
+    assert np.array_equal(raw, oracle.correlate_i64(q, T)), "int64 sums differ from the integer oracle"
+    spec = oracle.channelise(v, L)
+    prev, s_o, inv_o = None, [], []
+    for j in range(J):
+        _, s_j, inv_j, pop = oracle.calibrate(spec[j * T:j * T + ncal], prev=prev, return_populated=True)
+        assert (pop == 0) == (j == 1)
+        prev = (s_j, inv_j)
+        s_o.append(s_j)
+        inv_o.append(inv_j)
+    assert np.array_equal(sc[1], sc[0]), "an empty window must keep the previous scales"
+    for j in (0, 2):
+        assert np.max(np.abs(sc[j] / s_o[j] - 1)) < 1e-5
+    qo = np.concatenate([oracle.requantise(spec[j * T:(j + 1) * T], inv_o[j]) for j in range(J)])
+    dq = q.astype(np.int32) - qo.astype(np.int32)
+    assert np.abs(dq).max() <= 1 and np.count_nonzero(dq) <= 1e-4 * dq.size
+    # integration 2: one live sub-block in ten; with zeroed frames in the mean its
+    # sigma would be ~3x low and ~1/3 of the live codes would clip at +-127
+    live = np.any(q[2 * T:3 * T] != 0, axis=(1, 3))           # [T][n_in] populated frames
+    clipped = np.count_nonzero(np.abs(q[2 * T:3 * T].astype(np.int32)) == 127)
+    frac = clipped / max(1, np.count_nonzero(live) * L * 2)
+    log(f"int8 zeroed calibration: clip fraction {frac:.3g} over {np.count_nonzero(live)} live frames")
+    assert frac < 1e-3
+    w_orc = oracle.vis_weights(flags, subs)
+    vi = oracle.correlate_i64(qo, T).astype(np.float64)
+    v8 = (vi[..., 0] + 1j * vi[..., 1]) * np.stack([s.astype(np.float64) ** 2 for s in s_o])[:, :, None]
+    want = oracle.apply_weights(v8, w_orc)
+    got = vis.cpu().numpy().astype(np.complex128)
+    scale = np.linalg.norm(want, axis=-1, keepdims=True)
+    ok = scale[..., 0] > 0
+    err = np.linalg.norm(got - want, axis=-1)[ok] / scale[ok][:, 0]
+    assert err.max() < 1e-4
+    assert np.all(got[1] == 0)
+
+
+def test_weights_with_frames_straddling_sub_blocks():
+    # L = 1024 frames over 1280-sample sub-blocks: frames mix zeroed and live
+    # samples.  The weight still counts sub-blocks (it does not depend on L); a
+    # pair with w = 0 can then hold nonzero visibilities, which the normalisation
+    # leaves as they are.  Input 0 loses the even sub-blocks, input 1 the odd ones.
+    n_tiles, L, sub_len, subs = 2, 1024, 1280, 8
+    n_in = 2 * n_tiles
+    T = subs * sub_len // L
+    S = subs * sub_len
+    flags = np.zeros((n_in, subs), np.uint8)
+    flags[0, 0::2] = 1
+    flags[1, 1::2] = 1
+    v = synth.zero_subblocks(synth.gaussian_volts(n_in, S, seed=synth.MWAX_SEED + 7), flags, sub_len)
+    with Plan(make_config(n_tiles, L=L, T=T, xprec="fp32", max_samples=S)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        p.correlate()
+        vis = p.integrate(1).clone()
+        before = vis.clone()
+        w = mwax.vis_weights(torch.from_numpy(flags).cuda(), subs)
+        mwax.apply_weights(vis, w)
+        torch.cuda.synchronize()
+    w_orc = oracle.vis_weights(flags, subs)
+    p01 = 1 * 2 // 2 + 0
+    assert w_orc[0, p01] == 0 and w.cpu().numpy()[0, p01] == 0
+    ref = oracle.fx_correlate(v, L, T)
+    assert np.any(ref[0, :, p01] != 0), "straddling frames correlate although w = 0"
+    assert torch.equal(vis[0, :, p01], before[0, :, p01])
+    want = oracle.apply_weights(ref, w_orc)
+    got = vis.cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(got - want, axis=-1) / np.linalg.norm(want, axis=-1)
+    assert err.max() <= 1e-5

@@ -72,9 +72,16 @@ def test_printed_arithmetic():
     assert L6400 == PRINTED["fengine_fft_len"]
     assert PRINTED["block_samples_50ms"] // PRINTED["fengine_fft_len"] == PRINTED["subblocks_per_block"]
     assert PRINTED["fengine_fft_len"] / fs == pytest.approx(PRINTED["subblock_s"])
-    # the library derives L from the channel width; 6,400 is whole but not implemented
+    # the library derives L from the channel width: 200 Hz is the 6,400-point
+    # transform; a 250 ms gulp holds 50 of its 5 ms frames, a 50 ms block 10
+    d200 = mwax.derive(mwax.make_config(128, fine_chan_hz=PRINTED["ultrafine_chan_hz"],
+                                        int_time_s=PRINTED["min_integration_s"],
+                                        max_samples=PRINTED["block_samples_50ms"]))
+    assert d200.fft_len == PRINTED["fengine_fft_len"]
+    assert d200.spectra_per_int == 50 and d200.max_spectra == PRINTED["subblocks_per_block"]
+    # other whole lengths that are not powers of two stay unsupported
     with pytest.raises(mwax.MwaxError) as e:
-        mwax.derive(mwax.make_config(128, fine_chan_hz=200.0, int_time_s=0.25, max_samples=64000))
+        mwax.derive(mwax.make_config(128, fine_chan_hz=fs / 3200, int_time_s=0.25, max_samples=64000))
     assert e.value.status == mwax.MWAX_E_UNSUPPORTED
     # 10 kHz channels (fscrunch 50, Sec. 2.6) are a 128-point FFT
     d10k = mwax.derive(mwax.make_config(128, fine_chan_hz=PRINTED["fscrunch50_chan_hz"],

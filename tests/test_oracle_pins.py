@@ -813,3 +813,130 @@ def test_averaging_pins_catch_planted_slips(orc):
     assert averaging_ok(slip(), vis, L, F)              # the slip helper itself is right
     for bad in (slip(keep_dc=True), slip(full_ends=True), slip(centre=oc - 1)):
         assert not averaging_ok(bad, vis, L, F)
+
+
+# ---------------------------------------------------------------------------
+# Fractional delay and phase correction (Sec. 2.5.1 delay paragraph, Sec. 4.3)
+# ---------------------------------------------------------------------------
+def shifted_spectra(frames):
+    """fftshifted FFT of complex frames [M][L] -> [M][L][1] (numpy, FP64)."""
+    X = np.fft.fftshift(np.fft.fft(frames, axis=1), axes=1)
+    return X[:, :, None]
+
+
+def test_delay_whole_samples_is_a_circular_shift(orc):
+    # the delay theorem: delaying a frame by D whole samples (circularly) multiplies
+    # bin k by exp(-2 pi i k D / L); with nu_c = 0 the correction must equal the
+    # spectrum of the shifted frame, for either sign of D
+    L, M = 64, 3
+    x = rng(70).normal(size=(M, L)) + 1j * rng(71).normal(size=(M, L))
+    for D in (1, 5, -3, 17):
+        got = orc.delay_correct(shifted_spectra(x), np.full((1, 1), float(D)), L * M, 0.0)
+        want = shifted_spectra(np.roll(x, D, axis=1))
+        assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("k0", [-31, -1, 5, 31])
+def test_delay_fractional_tone_uses_signed_frequency(orc, k0):
+    # a tone at signed bin k0 sampled d samples late, exp(2 pi i k0 (q - d) / L),
+    # has bin k0 = L exp(-2 pi i k0 d / L): the gradient runs over the signed
+    # channel offset c - L/2, not the unsigned FFT bin
+    L, d = 64, 0.3125
+    q = np.arange(L)
+    clean = np.exp(2j * np.pi * k0 * q / L)[None, :]
+    late = np.exp(2j * np.pi * k0 * (q - d) / L)[None, :]
+    got = orc.delay_correct(shifted_spectra(clean), np.full((1, 1), d), L, 0.0)
+    c0 = (k0 + L // 2) % L
+    assert abs(got[0, c0, 0] - L * np.exp(-2j * np.pi * k0 * d / L)) < 1e-9 * L
+    assert abs(got[0, c0, 0] - shifted_spectra(late)[0, c0, 0]) < 1e-9 * L
+
+
+def test_delay_sky_frequency_offset(orc):
+    # L = 1: the only channel is the coarse-channel centre, so the gain is the
+    # offset exp(-2 pi i (nu_c / f_s) d) alone; the offset is the same in every
+    # channel of a longer transform, the gradient then varies across them
+    nu = synth.NU_C / synth.F_S
+    d = np.array([[0.37, -0.21]])
+    x = np.array([[[3.0 + 4.0j]], [[-1.0 + 2.0j]]])        # [M=2][L=1][n=1]
+    got = orc.delay_correct(x, d, 1, nu)
+    for m in range(2):
+        assert abs(got[m, 0, 0] - x[m, 0, 0] * np.exp(-2j * np.pi * nu * d[0, m])) < 1e-9
+    L = 16
+    ones = np.ones((1, L, 1), complex)
+    g = orc.delay_correct(ones, np.full((1, 1), 0.25), L, nu)[0, :, 0]
+    g0 = orc.delay_correct(ones, np.full((1, 1), 0.25), L, 0.0)[0, :, 0]
+    ratio = g / g0
+    assert np.allclose(ratio, np.exp(-2j * np.pi * nu * 0.25), atol=1e-12)
+    assert np.allclose(np.abs(g), 1.0, atol=1e-14)          # power (and calibration) unchanged
+    assert not np.allclose(g0, g0[0])                        # a gradient, not a constant
+
+
+def test_delay_steps_follow_the_stream(orc):
+    # a different whole-sample delay per step (step = 2 frames): every frame is
+    # the circular shift by its own step's delay, with the stream offset m0
+    L, M, step = 32, 6, 64
+    x = rng(72).normal(size=(M, L)) + 1j * rng(73).normal(size=(M, L))
+    m0 = 3                                  # frames 3..8 of the stream: steps 1..4
+    D = np.array([[0.0, 2.0, -5.0, 7.0, 11.0]])
+    got = orc.delay_correct(shifted_spectra(x), D, step, 0.0, m0=m0)
+    for m in range(M):
+        s = (m0 + m) * L // step
+        want = shifted_spectra(np.roll(x[m:m + 1], int(D[0, s]), axis=1))
+        assert np.max(np.abs(got[m:m + 1] - want)) < 1e-10 * np.max(np.abs(want))
+    with pytest.raises(ValueError):
+        orc.delay_correct(shifted_spectra(x), D[:, :3], step, 0.0, m0=m0)      # table too short
+
+
+def test_delay_point_source_phased_up(orc):
+    # the closed form of Sec. 4.3: a point source reaching input n tau_n late has
+    # visibility phase -2 pi nu (tau_1 - tau_2); applying the delays d_n = -tau_n f_s
+    # (advancing every path) leaves it real and positive in the source channel,
+    # at the same amplitude, for two sources at different frequencies
+    n_in, L, T, A = 6, 64, 400, 3.0
+    seed = 0x51
+    srcs = [synth.Source(A, 9), synth.Source(A, -20)]
+    v = synth.gaussian_volts(n_in, L * T, sigma=2.0, seed=seed, sources=srcs, L=L)
+    taus = synth.source_delays(n_in, seed)
+    spec = orc.channelise(v, L)
+    d = (-taus * synth.F_S)[:, None]
+    cor = orc.delay_correct(spec, d, L * T, synth.NU_C / synth.F_S)
+    V0 = orc.correlate(spec, T)[0]
+    V = orc.correlate(cor, T)[0]
+    for k0 in (9, -20):
+        c0 = (k0 + L // 2) % L
+        nu = synth.NU_C + k0 * synth.F_S / L
+        for a in range(n_in):
+            for b in range(a):
+                p = a * (a + 1) // 2 + b
+                want_before = np.angle(np.exp(-2j * np.pi * nu * (taus[a] - taus[b])))
+                assert abs(np.angle(V0[c0, p] * np.exp(-1j * want_before))) < 0.05
+                assert abs(np.angle(V[c0, p])) < 0.05
+                assert abs(abs(V[c0, p]) / (T * L * L * A * A) - 1) < 0.1
+
+
+def test_delay_pins_catch_planted_slips(orc):
+    # numpy copies of the correction with one slip each; the pins above reject them
+    L = 64
+
+    def slipped(spec, d, nu, slip):
+        c = np.arange(L) - L // 2
+        if slip == "unsigned":
+            c = (np.arange(L) + L // 2) % L            # the FFT bin instead of the signed offset
+        ph = c / L * d + (0.0 if slip == "no_offset" else nu * d)
+        g = np.exp((2j if slip == "sign" else -2j) * np.pi * ph)
+        return spec * g[None, :, None]
+
+    q = np.arange(L)
+    x = rng(74).normal(size=(1, L)) + 1j * rng(75).normal(size=(1, L))
+    want = shifted_spectra(np.roll(x, 3, axis=1))
+    assert np.max(np.abs(slipped(shifted_spectra(x), 3.0, 0.0, "sign") - want)) > 1e-3
+    tone = shifted_spectra(np.exp(2j * np.pi * -5 * q / L)[None, :])
+    c0 = -5 + L // 2
+    good = L * np.exp(-2j * np.pi * -5 * 0.3125 / L)
+    assert abs(slipped(tone, 0.3125, 0.0, "unsigned")[0, c0, 0] - good) > 1e-3 * L
+    assert abs(orc.delay_correct(tone, np.full((1, 1), 0.3125), L, 0.0)[0, c0, 0] - good) < 1e-9 * L
+    one = np.ones((1, L, 1), complex)
+    nu = synth.NU_C / synth.F_S
+    ref = orc.delay_correct(one, np.full((1, 1), 0.37), L, nu)
+    assert np.max(np.abs(slipped(one, 0.37, nu, "no_offset") - ref)) > 1e-3
+    assert np.max(np.abs(slipped(one, 0.37, nu, "none") - ref)) < 1e-9
