@@ -212,8 +212,35 @@ mwax_status mwax_auto_scales(mwax_plan p);
  * a null or misaligned pointer. */
 mwax_status mwax_get_scales(mwax_plan p, float *d_scales);
 
+/* Fractional delay and phase correction (Sec. 2.5.1, delay paragraph; Sec.
+ * 4.3).  The capture stage shifts each signal path by whole samples; the
+ * residual fractional delays, updated every step (5 ms in the paper), are
+ * applied to the frequency-domain samples before they are requantised: every
+ * sample of channel c of signal path n in a frame of step s is multiplied by
+ *   exp(-2 pi i ((c - L/2) / L + sky_freq_hz / coarse_bw) d[n][s]),
+ * a phase gradient across the channels (slope set by the delay alone) times a
+ * phase offset set by the coarse channel's sky frequency (the delay theorem:
+ * delaying by d samples multiplies the spectrum at sky frequency nu by
+ * exp(-2 pi i nu d / coarse_bw)).  The phase offset is reduced in FP64, the
+ * gains evaluated in FP32.
+ *   d_delays     : [n_inputs][n_steps] float32, device, delays to apply in
+ *                  samples (caller-owned; read by every later mwax_channelise
+ *                  until replaced, so it must stay valid and unchanged while
+ *                  that work runs).  NULL turns the correction off.
+ *   step_samples : samples per step, a multiple of L (6400 = 5 ms).
+ * Step 0 starts at the plan's current stream position; mwax_channelise
+ * returns MWAX_E_INVAL if a call reaches past step n_steps - 1.  The INT8
+ * calibration measures power, which the unit-modulus gains leave unchanged,
+ * so it runs on the uncorrected spectra.  MWAX_E_STATE with a block pending
+ * correlation; MWAX_E_UNSUPPORTED for instances of a batch (whose F-engine
+ * runs from batch tables); MWAX_E_INVAL for bad arguments.  mwax_reset turns
+ * the correction off. */
+mwax_status mwax_set_delays(mwax_plan p, const float *d_delays, int64_t n_steps, int64_t step_samples,
+                            double sky_freq_hz);
+
 /* Discard every integration in progress or not yet emitted and any pending
- * channelised block; the stream position returns to zero. */
+ * channelised block; the stream position returns to zero and delay
+ * correction is turned off. */
 mwax_status mwax_reset(mwax_plan p);
 
 /* Wait for the plan's stream.  MWAX_E_DEVICE if the runtime reports an error. */

@@ -625,6 +625,7 @@ mwax_status mwax_batch_create(const mwax_config *cfgs, int32_t n, void *hip_stre
             return fail(st, "instance %d: %s", i, m.c_str());
         }
         p->in_batch = true;
+        p->batched = true;
         b->inst.push_back(p);
         b->max_segs.push_back((int)(ceil_div(p->d.max_spectra, p->T) + 1));
         int gi = -1;

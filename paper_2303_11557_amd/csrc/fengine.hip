@@ -55,13 +55,24 @@ struct PrecTraits<MWAX_X_FP32> { static constexpr int G = 4, ES = 4; };
 // k = (r U + u) + L1 k2 with i = u L2 + k2; with P lanes per pass-2 transform,
 // lane r = k1 P + h holds k = k1 + L1 (i + L1 bitrev_P(h)).  Channel (k + L/2) mod L.
 template <int L, int XP>
-__device__ __forceinline__ int chan_of(int r, int i) {
+__device__ __forceinline__ int bin_of(int r, int i) {
     using SH = FftShape<L, XP>;
-    int k;
-    if constexpr (SH::P > 1) k = r / SH::P + SH::L1 * (i + SH::L1 * bitrev<SH::P>(r % SH::P));
-    else if constexpr (SH::L2 > 1) k = (r * SH::U + i / SH::L2) + SH::L1 * (i % SH::L2);
-    else k = i;
-    return (k + L / 2) & (L - 1);
+    if constexpr (SH::P > 1) return r / SH::P + SH::L1 * (i + SH::L1 * bitrev<SH::P>(r % SH::P));
+    else if constexpr (SH::L2 > 1) return (r * SH::U + i / SH::L2) + SH::L1 * (i % SH::L2);
+    else return i;
+}
+template <int L, int XP>
+__device__ __forceinline__ int chan_of(int r, int i) {
+    return (bin_of<L, XP>(r, i) + L / 2) & (L - 1);
+}
+
+// Gain of the fractional delay correction for signed bin ks (channel offset
+// c - L/2): exp(-2 pi i (ks alpha + phi)), alpha = d / L, phi = the frame's
+// phase offset (nu_c / f_s) d reduced to [-1/2, 1/2] revolutions.
+__device__ __forceinline__ float2 delay_gain(int ks, float alpha, float phi) {
+    float sn, cs;
+    sincospif(-2.0f * fmaf((float)ks, alpha, phi), &sn, &cs);
+    return make_float2(cs, sn);
 }
 
 // One radix-2 decimation-in-frequency stage across lanes h and h ^ B of a quad:
@@ -133,8 +144,9 @@ __device__ __forceinline__ float2 load_pair(const uint8_t *p) {
     return make_float2((float)(int8_t)w, (float)(int8_t)(w >> 8));
 }
 
-// The work of workgroup wg of nwg workgroups on the segment described by a.
-template <int L, int XP, bool STATS>
+// The work of workgroup wg of nwg workgroups on the segment described by a;
+// DELAY: apply the fractional delay and phase correction before requantising.
+template <int L, int XP, bool STATS, bool DELAY = false>
 __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const int nwg, uint8_t *smem) {
     using C = FCfg<L, XP>;
     constexpr int L1 = C::L1, L2 = C::L2, U = C::U, G = C::G, ES = C::ES, FPG = C::FPG;
@@ -285,8 +297,24 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             }
             dft_regs<L1>(v);
 
+            // this frame's delay (signal path n0 + nl) and phase offset
+            float dl_alpha = 0.0f, dl_phi = 0.0f;
+            if constexpr (DELAY) {
+                float d = 0.0f;
+                if (nl < nrows && f < fvalid)
+                    d = a.dl[(int64_t)(n0 + nl) * a.dl_ld + (a.dl_f0 + lf0 + f) / a.dl_fps];
+                const double ph = (double)d * a.dl_nu;
+                dl_phi = (float)(ph - rint(ph));
+                dl_alpha = d * (1.0f / (float)L);
+            }
+
             // consume output slot i (FFT bin of this lane) with value X
             auto emit = [&](int i, float2 X) {
+                if constexpr (DELAY) {
+                    const int k = bin_of<L, XP>(r, i);
+                    const float2 g = delay_gain(k < L / 2 ? k : k - L, dl_alpha, dl_phi);
+                    X = make_float2(X.x * g.x - X.y * g.y, X.x * g.y + X.y * g.x);
+                }
                 if constexpr (STATS) {
                     acc[i] += X.x * X.x + X.y * X.y;
                 } else {
@@ -447,10 +475,10 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     }
 }
 
-template <int L, int XP, bool STATS>
+template <int L, int XP, bool STATS, bool DELAY>
 __global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_kernel(FArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    fengine_body<L, XP, STATS>(a, blockIdx.x, gridDim.x, smem);
+    fengine_body<L, XP, STATS, DELAY>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Batched form: workgroups [block0[d], block0[d+1]) of the launch work on
@@ -485,17 +513,21 @@ hipError_t launch_L(const FArgs &a, hipStream_t s) {
     const int grid = fengine_grid(a.n_in, a.R, a.ngrp, stats);
     if (grid < 1) return hipSuccess;
     // allow dynamic LDS beyond the default limit (once per instantiation)
-    static bool attr_done[2] = {false, false};
-    if (!attr_done[stats]) {
-        const void *fn = stats ? reinterpret_cast<const void *>(&fengine_kernel<L, XP, true>)
-                               : reinterpret_cast<const void *>(&fengine_kernel<L, XP, false>);
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-        attr_done[stats] = true;
+    const int variant = stats ? 1 : (a.dl ? 2 : 0);
+    const void *fns[3] = {reinterpret_cast<const void *>(&fengine_kernel<L, XP, false, false>),
+                          reinterpret_cast<const void *>(&fengine_kernel<L, XP, true, false>),
+                          reinterpret_cast<const void *>(&fengine_kernel<L, XP, false, true>)};
+    static bool attr_done[3] = {false, false, false};
+    if (!attr_done[variant]) {
+        (void)hipFuncSetAttribute(fns[variant], hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+        attr_done[variant] = true;
     }
-    if (stats)
-        hipLaunchKernelGGL((fengine_kernel<L, XP, true>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
+    if (variant == 1)
+        hipLaunchKernelGGL((fengine_kernel<L, XP, true, false>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
+    else if (variant == 2)
+        hipLaunchKernelGGL((fengine_kernel<L, XP, false, true>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
     else
-        hipLaunchKernelGGL((fengine_kernel<L, XP, false>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
+        hipLaunchKernelGGL((fengine_kernel<L, XP, false, false>), dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
     return hipGetLastError();
 }
 

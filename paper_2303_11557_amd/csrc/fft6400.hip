@@ -122,7 +122,10 @@ struct Elem<MWAX_X_FP32> { static constexpr int ES = 4; };
 // every input, written to a.mid[n][frame][channel][re, im].  Statistics pass:
 // per-channel power sums and the populated-frame count of those frames, one
 // row [L + 1] per workgroup in a.stats (see calib_finish_channel).
-template <int XP, bool STATS>
+// DELAY: the fractional delay and phase correction of the frame's step, in the
+// epilogue: lane d holds the signed bins d + 400 j (j = -8 .. 7), so its gains
+// exp(-2 pi i ((d + 400 j) d_s / L + phi)) are b w^j with b, w from two sincos.
+template <int XP, bool STATS, bool DELAY>
 __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
     __shared__ float2 blk[kN1 * kPitch];
     constexpr int ES = Elem<XP>::ES;
@@ -206,6 +209,22 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
         }
         __syncthreads();
 
+        // this frame's delay: w^j = exp(-2 pi i 400 j d_s / L), j = 0 .. 8
+        float dl_alpha = 0.0f, dl_phi = 0.0f;
+        float2 pw[DELAY ? 9 : 1];
+        if constexpr (DELAY) {
+            const float dly = a.dl[n * a.dl_ld + (a.dl_f0 + m) / a.dl_fps];
+            const double ph = (double)dly * a.dl_nu;
+            dl_phi = (float)(ph - rint(ph));
+            dl_alpha = dly / (float)kL;
+            float sn, cs;
+            sincospif(-2.0f * dly * (400.0f / (float)kL), &sn, &cs);
+            pw[0] = make_float2(1.0f, 0.0f);
+            pw[1] = make_float2(cs, sn);
+#pragma unroll
+            for (int j = 2; j <= 8; ++j) pw[j] = cmul(pw[j - 1], pw[1]);
+        }
+
         // pass 3: DFTs d = 25 k2a + k1 over ra; bins d + 400 k2b
 #pragma unroll
         for (int slot = 0; slot < 2; ++slot) {
@@ -217,9 +236,20 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
 #pragma unroll
                 for (int q = 0; q < 16; ++q) z[q] = row[q];
                 dft_regs<16>(z);
+                float2 gb = make_float2(1.0f, 0.0f);
+                if constexpr (DELAY) {
+                    float sn, cs;
+                    sincospif(-2.0f * fmaf((float)d, dl_alpha, dl_phi), &sn, &cs);
+                    gb = make_float2(cs, sn);
+                }
 #pragma unroll
                 for (int k2b = 0; k2b < 16; ++k2b) {
-                    const float2 X = z[k2b];
+                    float2 X = z[k2b];
+                    if constexpr (DELAY) {
+                        // bins past L/2 are the negative frequencies d + 400 (k2b - 16)
+                        const float2 wj = k2b < 8 ? pw[k2b] : make_float2(pw[16 - k2b].x, -pw[16 - k2b].y);
+                        X = cmul(X, cmul(gb, wj));
+                    }
                     if constexpr (STATS) {
                         acc[slot * 16 + k2b] += X.x * X.x + X.y * X.y;
                     } else {
@@ -316,8 +346,9 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(CornerArgs a) {
 
 template <int XP>
 hipError_t launch_fft_xp(const FArgs &a, bool stats, int grid, hipStream_t s) {
-    if (stats) hipLaunchKernelGGL((fft6400_kernel<XP, true>), dim3((unsigned)grid), dim3(kT), 0, s, a);
-    else hipLaunchKernelGGL((fft6400_kernel<XP, false>), dim3((unsigned)grid), dim3(kT), 0, s, a);
+    if (stats) hipLaunchKernelGGL((fft6400_kernel<XP, true, false>), dim3((unsigned)grid), dim3(kT), 0, s, a);
+    else if (a.dl) hipLaunchKernelGGL((fft6400_kernel<XP, false, true>), dim3((unsigned)grid), dim3(kT), 0, s, a);
+    else hipLaunchKernelGGL((fft6400_kernel<XP, false, false>), dim3((unsigned)grid), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 

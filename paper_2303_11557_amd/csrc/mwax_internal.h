@@ -72,6 +72,13 @@ struct FArgs {
                             // per channel, then the count of populated frames
     uint8_t *mid;           // L = 6400: frame-major spectra [N_in][mid_frames][L][2]
     int64_t mid_frames;     // frames per input row of mid
+    // fractional delay and phase correction (NULL dl: none): frame f of the
+    // segment uses the delay dl[n * dl_ld + (dl_f0 + f) / dl_fps] (samples)
+    const float *dl;
+    int64_t dl_ld;          // steps per input row of dl
+    int64_t dl_f0;          // table frame index of the segment's first frame
+    int32_t dl_fps;         // frames per delay step
+    double dl_nu;           // sky frequency of the coarse channel centre / f_s
 };
 
 constexpr int kStatsMaxWG = 1024;   // calibration partial rows per launch (max)

@@ -61,6 +61,15 @@ struct mwax_plan_s {
     bool fixed_mode = false;
     bool in_batch = false;          // owned by a batch or stream (destroyed with it)
     bool static_ws = false;         // workspace lives in the library's static device array
+    bool batched = false;           // an instance of a batch (its F-engine runs from batch tables)
+    // fractional delay and phase correction (mwax_set_delays): caller's table
+    // [n_in][dl_steps] of delays in samples; step s covers stream frames
+    // dl_pos0 + s dl_fps .. dl_pos0 + (s + 1) dl_fps - 1
+    const float *dl = nullptr;
+    int64_t dl_steps = 0;
+    int32_t dl_fps = 0;
+    int64_t dl_pos0 = 0;
+    double dl_nu = 0.0;             // sky frequency / coarse bandwidth
     // Clear a slot's integrators when its integration is emitted.  Off only where
     // every integration's first X-engine flush overwrites the whole slot
     // (whole-segment INT8/FP16 work of a batch); mwax_correlate clears a slot

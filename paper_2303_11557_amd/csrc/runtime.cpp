@@ -197,6 +197,13 @@ FArgs mwax::fengine_args(mwax_plan p, const Segment &s, const int8_t *volts, int
     a.half_scale = std::ldexp(1.0f, -fp16_exponent(p->L));
     a.mid = p->mid;
     a.mid_frames = p->d.max_spectra;
+    if (p->dl) {
+        a.dl = p->dl;
+        a.dl_ld = p->dl_steps;
+        a.dl_f0 = p->g_chan + s.frame0 - p->dl_pos0;   // g_chan: stream frame of the call's start
+        a.dl_fps = p->dl_fps;
+        a.dl_nu = p->dl_nu;
+    }
     return a;
 }
 
@@ -417,6 +424,12 @@ mwax_status mwax_channelise(mwax_plan p, const int8_t *d_volts, int64_t n_sample
         return fail(MWAX_E_INVAL, "ld_samples = %lld must be >= n_samples and a multiple of 8", (long long)ld_samples);
     if (p->pending) return fail(MWAX_E_STATE, "the previous channelised block has not been correlated");
     const int64_t M = n_samples / p->L;
+    if (p->dl) {
+        const int64_t last_step = (p->g_chan + M - 1 - p->dl_pos0) / p->dl_fps;
+        if (last_step >= p->dl_steps)
+            return fail(MWAX_E_INVAL, "the delay table covers %lld steps; this call reaches step %lld",
+                        (long long)p->dl_steps, (long long)last_step);
+    }
     std::vector<Segment> segs;
     mwax_status st = plan_segments(p, M, segs);
     if (st != MWAX_OK) return st;
@@ -618,6 +631,30 @@ mwax_status mwax_auto_scales(mwax_plan p) {
     return ok();
 }
 
+mwax_status mwax_set_delays(mwax_plan p, const float *d_delays, int64_t n_steps, int64_t step_samples,
+                            double sky_freq_hz) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (p->batched) return fail(MWAX_E_UNSUPPORTED, "delay correction is not applied by batches");
+    if (p->pending) return fail(MWAX_E_STATE, "the previous channelised block has not been correlated");
+    if (!d_delays) {
+        p->dl = nullptr;
+        p->dl_steps = 0;
+        return ok();
+    }
+    if (((uintptr_t)d_delays & 3) != 0) return fail(MWAX_E_INVAL, "delay table must be 4-byte aligned");
+    if (n_steps < 1) return fail(MWAX_E_INVAL, "n_steps must be >= 1");
+    if (step_samples < p->L || step_samples % p->L != 0 || step_samples / p->L > 0x7fffffff)
+        return fail(MWAX_E_INVAL, "step_samples = %lld must be a positive multiple of L = %d",
+                    (long long)step_samples, p->L);
+    if (!std::isfinite(sky_freq_hz)) return fail(MWAX_E_INVAL, "sky frequency must be finite");
+    p->dl = d_delays;
+    p->dl_steps = n_steps;
+    p->dl_fps = (int32_t)(step_samples / p->L);
+    p->dl_pos0 = p->g_chan;
+    p->dl_nu = sky_freq_hz / p->cfg.coarse_bw_hz;
+    return ok();
+}
+
 mwax_status mwax_reset(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     hipError_t e = launch_fill_zero(p->integ, p->slot_bytes * p->nslots, p->stream);
@@ -628,6 +665,8 @@ mwax_status mwax_reset(mwax_plan p) {
     std::fill(p->slot_count.begin(), p->slot_count.end(), 0);
     p->g_chan = 0;
     p->next_emit = 0;
+    p->dl = nullptr;
+    p->dl_steps = 0;
     p->pending = false;
     p->have_block = false;
     p->segs.clear();

@@ -25,6 +25,7 @@ EXPORTS = (
     "mwax_plan_derive", "mwax_plan_create", "mwax_plan_destroy", "mwax_plan_get_dims",
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
+    "mwax_set_delays",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
@@ -117,6 +118,7 @@ def lib():
             "mwax_set_scales": [vp, P(ctypes.c_float)],
             "mwax_auto_scales": [vp],
             "mwax_get_scales": [vp, vp],
+            "mwax_set_delays": [vp, vp, i64, i64, ctypes.c_double],
             "mwax_reset": [vp],
             "mwax_sync": [vp],
             "mwax_set_timing": [vp, i32],
@@ -308,6 +310,21 @@ class Plan:
         assert out.is_cuda and out.dtype == t.float32 and out.is_contiguous() and out.numel() >= self.L
         _check(lib().mwax_get_scales(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def set_delays(self, delays, step_samples=6400, sky_freq_hz=0.0):
+        """Fractional delay and phase correction for the following channelise calls:
+        delays = float32 cuda tensor [n_inputs][n_steps] (samples), kept alive by the
+        caller; None turns it off."""
+        if delays is None:
+            _check(lib().mwax_set_delays(self.h, None, 0, 0, 0.0))
+            self._delays = None
+            return
+        t = self.torch
+        assert delays.is_cuda and delays.dtype == t.float32 and delays.is_contiguous() and delays.dim() == 2
+        assert delays.shape[0] == self.n_in
+        _check(lib().mwax_set_delays(self.h, ctypes.c_void_p(delays.data_ptr()), delays.shape[1],
+                                     int(step_samples), float(sky_freq_hz)))
+        self._delays = delays        # keep the table alive while the plan may read it
 
     def reset(self):
         _check(lib().mwax_reset(self.h))

@@ -171,13 +171,16 @@ def test_stream_output_ring_back_pressure():
             slot, _ = s.acquire(wait_ms=-1)
             s.copy_in(slot, hv[:, b * BLOCK:(b + 1) * BLOCK])
             if b == 2:
+                # block 2 takes the entries of block 0, which poll has not returned
                 with pytest.raises(mwax.MwaxError) as e:
-                    s.submit(slot, 0, s.now())            # block 0 not returned by poll yet
+                    s.submit(slot, 0, s.now())
                 assert e.value.status == mwax.MWAX_E_STATE and "poll" in str(e.value)
-            if b >= 2:
-                wait_block(b - 2)
+                wait_block(0)
+                read(0)
+                read(1)
+                torch.cuda.synchronize()                   # read before block 2 reuses them
             s.submit(slot, 0, s.now())
-            if b >= 1:
+            if b >= 2:
                 wait_block(b - 1)                          # block b may still be running
                 read(2 * b - 2)
                 read(2 * b - 1)

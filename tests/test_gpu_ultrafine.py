@@ -162,11 +162,18 @@ def test_fft6400_int8_end_to_end():
     qo = oracle.requantise(spec, inv_o)
     d = q.astype(np.int32) - qo.astype(np.int32)
     assert np.abs(d).max() <= 1 and np.count_nonzero(d) <= 1e-4 * d.size
+    # against FP64: the error of the encoding itself (30 spectra leave the
+    # requantisation noise of the cross pairs barely averaged), measured on the
+    # oracle's own INT8 chain
     ref = oracle.correlate(spec, T)
     got = (raw[..., 0] + 1j * raw[..., 1]) * (sc.astype(np.float64) ** 2)[:, :, None]
-    err = rel_frob(got, ref)
-    log(f"fft6400 int8 end to end: max per-channel rel-Frobenius vs FP64 {err.max():.3g}")
-    assert err.max() < 3e-3
+    vi = oracle.correlate_i64(qo, T).astype(np.float64)
+    v8 = (vi[..., 0] + 1j * vi[..., 1]) * (s_o.astype(np.float64) ** 2)[None, :, None]
+    err, e_chain = rel_frob(got, ref), rel_frob(v8, ref)
+    log(f"fft6400 int8 end to end: max per-channel rel-Frobenius vs FP64 {err.max():.3g} "
+        f"(oracle int8 chain {e_chain.max():.3g})")
+    assert err.max() < 1.25 * e_chain.max() + 1e-4
+    assert rel_frob(got, v8).max() < 1e-4
 
 
 def test_fft6400_rejected_by_batches():
