@@ -126,6 +126,20 @@ mwax_status mwax_plan_derive(const mwax_config *cfg, mwax_dims *out);
  * Errors: MWAX_E_INVAL (configuration), MWAX_E_NOMEM, MWAX_E_DEVICE. */
 mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): like
+ * mwax_plan_create, but the plan's workspace is carved out of a static device
+ * array of the library (64 MiB per device, held from library load until the
+ * process ends) instead of being allocated; no device allocation routine is
+ * called.  Every later call on the plan behaves as for mwax_plan_create.  At
+ * most one such plan exists per device at a time (they would share the
+ * array): MWAX_E_STATE while another lives; mwax_plan_destroy releases it.
+ * The workspace is initialised here (integrators cleared, scales 1), so it
+ * keeps nothing of the previous plan.  Errors: MWAX_E_INVAL for a
+ * configuration, or a workspace (mwax_dims.workspace_bytes, each buffer
+ * rounded up to 256 bytes) larger than 64 MiB; MWAX_E_DEVICE. */
+mwax_status mwax_plan_create_noalloc(const mwax_config *cfg, void *hip_stream, mwax_plan *out);
+
 /* Release the plan and its workspace (waits for its stream first).  NULL is
  * accepted and ignored. */
 mwax_status mwax_plan_destroy(mwax_plan p);

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "plan.h"
 
 namespace mwax {
@@ -107,6 +109,24 @@ mwax_status mwax::derive(const mwax_config *cfg, mwax_dims *o) {
     return MWAX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static workspace for plans created by mwax_plan_create_noalloc: a file-scope
+// device array (each device that loads the library holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: the
+// device address of each device's copy is looked up once, with that device
+// current, and kept in g_scratch_ptr.  At most one such plan lives on a device
+// at a time (they would share the array).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;   // 64 MiB per device
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kScratchMaxDevices] = {};
+bool g_scratch_live[kScratchMaxDevices] = {};
+}  // namespace
+
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 void mwax::free_plan(mwax_plan p) {
     if (!p) return;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
@@ -116,7 +136,10 @@ void mwax::free_plan(mwax_plan p) {
         (void)hipEventDestroy(e.b);
     }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    if (!p->static_ws) {
+    if (p->static_ws) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (p->device >= 0 && p->device < kScratchMaxDevices) g_scratch_live[p->device] = false;
+    } else {
         (void)hipFree(p->chan);
         (void)hipFree(p->integ);
         (void)hipFree(p->scales);
@@ -386,7 +409,7 @@ mwax_status create_plan(const mwax_config *cfg, void *hip_stream, mwax_plan *out
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         mwax_status r = hip_fail(e, "plan initialisation");
-        if (p->static_ws) delete p;   // nothing allocated
+        if (p->static_ws) delete p;   // nothing allocated; the caller holds the workspace lock
         else free_plan(p);
         return r;
     }
@@ -398,6 +421,29 @@ mwax_status create_plan(const mwax_config *cfg, void *hip_stream, mwax_plan *out
 
 mwax_status mwax_plan_create(const mwax_config *cfg, void *hip_stream, mwax_plan *out) {
     return create_plan(cfg, hip_stream, out, nullptr, 0);
+}
+
+mwax_status mwax_plan_create_noalloc(const mwax_config *cfg, void *hip_stream, mwax_plan *out) {
+    if (!out) return fail(MWAX_E_INVAL, "null output handle");
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= kScratchMaxDevices) return fail(MWAX_E_UNSUPPORTED, "device %d: no static workspace", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // once per device, with that device current: the address of its copy
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "static workspace address");
+        if (!ptr) return fail(MWAX_E_DEVICE, "static workspace address: null");
+        g_scratch_ptr[dev] = (uint8_t *)ptr;
+    }
+    if (g_scratch_live[dev])
+        return fail(MWAX_E_STATE, "device %d already has a plan in the static workspace: destroy it first", dev);
+    mwax_status st = create_plan(cfg, hip_stream, out, g_scratch_ptr[dev], kScratchBytes);
+    if (st == MWAX_OK) g_scratch_live[dev] = true;
+    return st;
 }
 
 mwax_status mwax_plan_destroy(mwax_plan p) {

@@ -22,7 +22,7 @@ _PREC = {"fp32": X_FP32, "fp16": X_FP16, "int8": X_INT8}
 _ORDER = {"tri": ORDER_CHAN_TRI, "tile_bl": ORDER_TILE_BL}
 
 EXPORTS = (
-    "mwax_plan_derive", "mwax_plan_create", "mwax_plan_destroy", "mwax_plan_get_dims",
+    "mwax_plan_derive", "mwax_plan_create", "mwax_plan_create_noalloc", "mwax_plan_destroy", "mwax_plan_get_dims",
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
     "mwax_set_delays",
@@ -107,6 +107,7 @@ def lib():
         sig = {
             "mwax_plan_derive": [P(Config), P(Dims)],
             "mwax_plan_create": [P(Config), vp, P(vp)],
+            "mwax_plan_create_noalloc": [P(Config), vp, P(vp)],
             "mwax_plan_destroy": [vp],
             "mwax_plan_get_dims": [vp, P(Dims)],
             "mwax_channelise": [vp, vp, i64, i64],
@@ -188,9 +189,10 @@ class Plan:
     """One correlator plan on the current device and torch's current stream.
 
     A plan that belongs to a batch (``Batch.plans``) wraps the batch's handle and
-    is released with the batch."""
+    is released with the batch.  noalloc=True creates the plan in the library's
+    static device workspace (mwax_plan_create_noalloc)."""
 
-    def __init__(self, cfg: Config, stream=None, _handle=None):
+    def __init__(self, cfg: Config, stream=None, _handle=None, noalloc=False):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -200,8 +202,8 @@ class Plan:
                 stream = torch.cuda.current_stream()
             self.stream = stream
             h = ctypes.c_void_p()
-            _check(lib().mwax_plan_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
-                                          ctypes.byref(h)))
+            create = lib().mwax_plan_create_noalloc if noalloc else lib().mwax_plan_create
+            _check(create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         else:
             self.stream = None
             h = _handle
