@@ -76,10 +76,14 @@ def _load():
         lib.orc_fscrunch.argtypes = [_c_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_f64p]
         lib.orc_delay_correct.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                           _c_f64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_double]
+        lib.orc_beamform.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _c_f64p,
+                                     ctypes.c_int, _c_f64p]
+        lib.orc_incoherent.argtypes = [_c_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, _c_f64p]
         for f in ("orc_dft", "orc_fft", "orc_channelise", "orc_correlate", "orc_correlate_full",
                   "orc_correlate_i64", "orc_requantise", "orc_calibrate", "orc_round_fp16",
                   "orc_pack_tilebl", "orc_vis_weights", "orc_apply_weights", "orc_fscrunch",
-                  "orc_delay_correct"):
+                  "orc_delay_correct", "orc_beamform", "orc_incoherent"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -311,3 +315,29 @@ def delay_correct(spec, delays, step_samples: int, nu_over_fs: float, m0: int = 
     _check(_load().orc_delay_correct(_ptr(sp, _c_f64p), M, L, n, int(m0), _ptr(d, _c_f64p), d.shape[1],
                                      int(step_samples), float(nu_over_fs)), "delay_correct")
     return _to_complex(sp)
+
+
+def beamform(spec, weights) -> np.ndarray:
+    """Coherent tied-array beams (Sec. 4.4): spectra [M][L][n] and complex
+    weights [L][nb][n] -> beams [M][L][nb] = sum_n w spec."""
+    sp = _as_pairs(np.asarray(spec, dtype=np.complex128))
+    M, L, n = sp.shape[:3]
+    w = _as_pairs(np.asarray(weights, dtype=np.complex128))
+    if w.shape[0] != L or w.shape[2] != n:
+        raise ValueError("weights must be [L][n_beams][n_inputs]")
+    nb = w.shape[1]
+    out = np.empty((M, L, nb, 2), np.float64)
+    _check(_load().orc_beamform(_ptr(sp, _c_f64p), M, L, n, _ptr(w, _c_f64p), nb, _ptr(out, _c_f64p)),
+           "beamform")
+    return _to_complex(out)
+
+
+def incoherent(spec, t_avg: int, f_avg: int) -> np.ndarray:
+    """Incoherent beam (Sec. 4.4): detected power summed over the inputs of each
+    polarisation, t_avg spectra and f_avg channels -> [M/t_avg][L/f_avg][2]."""
+    sp = _as_pairs(np.asarray(spec, dtype=np.complex128))
+    M, L, n = sp.shape[:3]
+    out = np.empty((M // max(t_avg, 1), L // max(f_avg, 1), 2), np.float64)
+    _check(_load().orc_incoherent(_ptr(sp, _c_f64p), M, L, n, int(t_avg), int(f_avg), _ptr(out, _c_f64p)),
+           "incoherent")
+    return out

@@ -602,3 +602,55 @@ int orc_delay_correct(double *spec, int64_t M, int L, int n, int64_t m0, const d
     }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Tied-array beamforming (Sec. 4.4) from the channelised voltages.
+ * Coherent beams: the signal paths, each weighted by a complex gain that
+ * aligns it for the beam's pointing, are summed coherently per channel and
+ * spectrum:
+ *   beams[m][c][b] = sum_n w[c][b][n] spec[m][c][n]
+ *   spec : [M][L][n][2], w : [L][nb][n][2], beams : [M][L][nb][2].
+ * Incoherent beam: the detected power of every signal path of each
+ * polarisation p (input n = 2 tile + p) is summed over the inputs, t_avg
+ * consecutive spectra and f_avg consecutive channels:
+ *   out[j][o][p] = sum_{m = j t_avg}^{(j+1) t_avg - 1} sum_{c = o f_avg}^{(o+1) f_avg - 1}
+ *                  sum_{n : n mod 2 = p} |spec[m][c][n]|^2
+ *   out : [M / t_avg][L / f_avg][2] (t_avg divides M, f_avg divides L).
+ * ------------------------------------------------------------------------- */
+int orc_beamform(const double *spec, int64_t M, int L, int n, const double *w, int nb, double *beams) {
+    if (M < 0 || L < 1 || n < 1 || nb < 1) return ORC_EINVAL;
+    for (int64_t m = 0; m < M; ++m)
+        for (int c = 0; c < L; ++c)
+            for (int b = 0; b < nb; ++b) {
+                double re = 0.0, im = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const double *x = spec + ((m * L + c) * (int64_t)n + k) * 2;
+                    const double *g = w + (((int64_t)c * nb + b) * n + k) * 2;
+                    re += g[0] * x[0] - g[1] * x[1];
+                    im += g[0] * x[1] + g[1] * x[0];
+                }
+                double *y = beams + ((m * L + c) * (int64_t)nb + b) * 2;
+                y[0] = re;
+                y[1] = im;
+            }
+    return ORC_OK;
+}
+
+int orc_incoherent(const double *spec, int64_t M, int L, int n, int t_avg, int f_avg, double *out) {
+    if (M < 0 || L < 1 || n < 1 || t_avg < 1 || f_avg < 1 || M % t_avg || L % f_avg) return ORC_EINVAL;
+    const int64_t J = M / t_avg;
+    const int O = L / f_avg;
+    for (int64_t j = 0; j < J; ++j)
+        for (int o = 0; o < O; ++o)
+            for (int p = 0; p < 2; ++p) {
+                double acc = 0.0;
+                for (int64_t m = j * t_avg; m < (j + 1) * t_avg; ++m)
+                    for (int c = o * f_avg; c < (o + 1) * f_avg; ++c)
+                        for (int k = p; k < n; k += 2) {
+                            const double *x = spec + ((m * L + c) * (int64_t)n + k) * 2;
+                            acc += x[0] * x[0] + x[1] * x[1];
+                        }
+                out[(j * O + o) * 2 + p] = acc;
+            }
+    return ORC_OK;
+}

@@ -940,3 +940,83 @@ def test_delay_pins_catch_planted_slips(orc):
     ref = orc.delay_correct(one, np.full((1, 1), 0.37), L, nu)
     assert np.max(np.abs(slipped(one, 0.37, nu, "no_offset") - ref)) > 1e-3
     assert np.max(np.abs(slipped(one, 0.37, nu, "none") - ref)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Tied-array beamforming (Sec. 4.4)
+# ---------------------------------------------------------------------------
+def test_beamform_phased_source_closed_form(orc):
+    # an exact tone reaching input n with phase i^p_n: weights conj(i^p_n) phase the
+    # inputs up, so the coherent beam holds N A L in the tone channel (power
+    # N^2 A^2 L^2, N times the incoherent sum N A^2 L^2); other channels are 0;
+    # a beam pointed elsewhere (weights i^p_n) sums to a closed form too
+    n, L, M, A, k0 = 8, 16, 3, 20, 4
+    ph = np.array([0, 1, 2, 3, 1, 1, 0, 2])
+    v = synth.tone_volts(n, L * M, L, k0, A, ph)
+    spec = orc.channelise(v, L)
+    c0 = (k0 + L // 2) % L
+    w = np.zeros((L, 2, n), complex)
+    w[:, 0, :] = (1j ** ph).conj()
+    w[:, 1, :] = 1j ** ph
+    B = orc.beamform(spec, w)
+    assert B.shape == (M, L, 2)
+    assert np.array_equal(B[:, c0, 0], np.full(M, n * A * L, complex))
+    other = np.sum((1j ** ph) ** 2) * A * L
+    assert np.allclose(B[:, c0, 1], other * (1j ** (np.arange(M) * 0)), atol=1e-9)
+    assert np.max(np.abs(np.delete(B, c0, axis=1))) < 1e-9
+    inc = orc.incoherent(spec, M, L)          # everything in one bin per polarisation
+    assert inc.shape == (1, 1, 2)
+    assert inc[0, 0].sum() == pytest.approx(M * n * A * A * L * L, rel=1e-12)
+    assert np.abs(B[0, c0, 0]) ** 2 == pytest.approx(n * inc[0, 0].sum() / M, rel=1e-12)
+
+
+def test_beamform_brute_force(orc):
+    # tiny case written out in pure Python
+    n, L, M, nb = 3, 4, 2, 2
+    spec = rng(80).normal(size=(M, L, n)) + 1j * rng(81).normal(size=(M, L, n))
+    w = rng(82).normal(size=(L, nb, n)) + 1j * rng(83).normal(size=(L, nb, n))
+    B = orc.beamform(spec, w)
+    for m in range(M):
+        for c in range(L):
+            for b in range(nb):
+                want = sum(complex(w[c, b, k]) * complex(spec[m, c, k]) for k in range(n))
+                assert abs(B[m, c, b] - want) < 1e-12
+
+
+def test_incoherent_parseval_and_grouping(orc):
+    # per spectrum and polarisation, the power over all channels is L times the
+    # time-domain power of the frame (Parseval, exact integers); grouping sums
+    # consecutive spectra and channels
+    n, L, M = 6, 32, 8
+    v = rand_volts(n, L * M, seed=84, amp=50)
+    spec = orc.channelise(v, L)
+    full = orc.incoherent(spec, 1, L)                     # [M][1][2]
+    x = v.astype(np.int64)
+    for m in range(M):
+        fr = x[:, m * L:(m + 1) * L]
+        for p in range(2):
+            assert full[m, 0, p] == pytest.approx(L * np.sum(fr[p::2] ** 2), rel=1e-12)
+    g = orc.incoherent(spec, 4, 8)                        # [2][4][2]
+    fine = orc.incoherent(spec, 1, 1)                     # [M][L][2]
+    assert np.allclose(g, fine.reshape(2, 4, 4, 8, 2).sum(axis=(1, 3)), rtol=1e-12)
+    with pytest.raises(ValueError):
+        orc.incoherent(spec, 3, 8)                        # 3 does not divide 8 spectra
+
+
+def test_beamform_pins_catch_planted_slips(orc):
+    n, L, M, A, k0 = 8, 16, 2, 20, 4
+    ph = np.array([0, 1, 2, 3, 3, 2, 1, 0])
+    spec = orc.channelise(synth.tone_volts(n, L * M, L, k0, A, ph), L)
+    c0 = (k0 + L // 2) % L
+    w = np.broadcast_to((1j ** ph).conj(), (L, 1, n))
+    good = np.einsum("cbn,mcn->mcb", w, spec)                        # the definition, in numpy
+    assert np.allclose(orc.beamform(spec, w), good, atol=1e-9)
+    slip_conj = np.einsum("cbn,mcn->mcb", w.conj(), spec)            # weights conjugated
+    assert abs(abs(slip_conj[0, c0, 0]) - n * A * L) > 1.0
+    v = rand_volts(n, L * M, seed=85, amp=20)
+    v[1::2] *= 3                                                      # Y paths 3x louder
+    sp = orc.channelise(v, L)
+    inc = orc.incoherent(sp, M, L)[0, 0]
+    assert inc[1] > 5 * inc[0]                                        # so a swap is visible
+    slip_pol = orc.incoherent(sp[:, :, ::-1], M, L)[0, 0]             # polarisations swapped
+    assert abs(slip_pol[0] - inc[0]) > 0.5 * inc[0]
