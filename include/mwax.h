@@ -189,6 +189,34 @@ mwax_status mwax_load_channelised(mwax_plan p, const void *d_chan, int64_t n_spe
 mwax_status mwax_read_channelised(mwax_plan p, void *d_out, int64_t max_spectra,
                                   int64_t *n_spectra);
 
+/* Tied-array beamforming (Sec. 4.4) from the last channelised block (the
+ * voltages the X-engine correlates: INT8 codes times the channel's scale s_c,
+ * binary16 values times 2^e, or FP32 spectra), before or after mwax_correlate.
+ *
+ * mwax_beamform: coherent beams
+ *   out[m][c][b] = sum_n w[c][b][n] X_n[m, c]
+ * d_weights [L][n_beams][n_inputs] complex64 (e.g. the phase factors that
+ * align every signal path for beam b's pointing, zeros for the paths a beam
+ * leaves out); d_out [n_spectra][L][n_beams] complex64 with n_spectra =
+ * the block's spectra (<= max_spectra), written to *n_spectra.  Sums on the
+ * FP32 matrix cores.
+ *
+ * mwax_beamform_incoherent: the incoherent beam, detected power summed over
+ * the inputs of each polarisation (input n = 2 tile + p), t_avg consecutive
+ * spectra and f_avg consecutive channels:
+ *   out[j][o][p] = sum_{m in j, c in o, n mod 2 = p} |X_n[m, c]|^2
+ * d_out [n_spectra / t_avg][L / f_avg][2] float32 (FP64 sums), needing
+ * max_bins >= (n_spectra / t_avg) (L / f_avg); *n_time_bins receives
+ * n_spectra / t_avg.  t_avg must divide the block's spectra and f_avg divide L.
+ *
+ * Both: device pointers, 8-byte (weights, beams) / 4-byte (power) aligned,
+ * caller-owned; enqueued on the plan's stream.  MWAX_E_STATE if nothing has
+ * been channelised, MWAX_E_INVAL for bad arguments or too small an output. */
+mwax_status mwax_beamform(mwax_plan p, const void *d_weights, int32_t n_beams, void *d_out, int64_t max_spectra,
+                          int64_t *n_spectra);
+mwax_status mwax_beamform_incoherent(mwax_plan p, int32_t t_avg, int32_t f_avg, float *d_out, int64_t max_bins,
+                                     int64_t *n_time_bins);
+
 /* X-engine (Sec. 2.5.2): accumulate the last channelised block into the
  * device integrators.  MWAX_E_STATE if there is no fresh channelised block. */
 mwax_status mwax_correlate(mwax_plan p);

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libmwax.so")
 SYNTH_SRC = os.path.join(ROOT, "synth", "synth.hip")
 SYNTH_LIB = os.path.join(ROOT, "synth", "libsynth.so")
 
-SOURCES = ["runtime.cpp", "batch.cpp", "stream.cpp", "fengine.hip", "fft6400.hip", "xengine.hip", "pack.hip", "weights.hip", "average.hip"]
+SOURCES = ["runtime.cpp", "batch.cpp", "stream.cpp", "fengine.hip", "fft6400.hip", "xengine.hip", "pack.hip", "weights.hip", "average.hip", "beamform.hip"]
 ARCH = "gfx950"
 
 

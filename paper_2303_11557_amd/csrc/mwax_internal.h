@@ -116,6 +116,41 @@ int fft6400_lds_bytes();
 hipError_t launch_fft6400(int xprec, const FArgs &a, hipStream_t s);
 hipError_t launch_corner_turn(int esize, const CornerArgs &a, hipStream_t s);
 
+// Tied-array beamforming (Sec. 4.4) from the channel-major buffer, one
+// segment (one integration's spectra, one scale per channel) per launch.
+struct BeamArgs {
+    const uint8_t *chan;    // [L][NG][N_in][32 B]
+    int64_t NG;
+    int64_t grp0;           // first row group of the segment
+    int64_t nframes;        // spectra of the segment
+    int64_t m0;             // output index of the segment's first spectrum
+    const float *scales;    // INT8: s_c [L] of the segment's integration; else NULL
+    float post;             // FP16: 2^e; else 1
+    int32_t n_in;
+    int32_t L;
+    int32_t nb;             // beams
+    const float2 *w;        // [L][nb][N_in] weights
+    float2 *out;            // [M][L][nb]
+};
+hipError_t launch_beamform(int esize, const BeamArgs &a, hipStream_t s);
+constexpr int kIncohMaxSeg = 64;
+struct IncohArgs {
+    const uint8_t *chan;
+    int64_t NG;
+    int32_t n_in;
+    int32_t L;
+    int32_t t_avg, f_avg;   // spectra and channels per output bin
+    int32_t n_o;            // L / f_avg
+    int64_t n_j;            // block spectra / t_avg
+    float post;
+    int32_t nseg;
+    int64_t seg_m0[kIncohMaxSeg];          // block index of each segment's first spectrum
+    int64_t seg_grp0[kIncohMaxSeg];
+    const float *seg_scales[kIncohMaxSeg]; // INT8 s_c per segment; else NULL
+    float *out;             // [n_j][n_o][2]
+};
+hipError_t launch_incoherent(int esize, const IncohArgs &a, hipStream_t s);
+
 // Reads a workgroup-uniform table entry through the constant address space: the
 // compiler may then reload its fields where they are used (as it does for kernel
 // arguments) instead of holding them in registers for the whole kernel.

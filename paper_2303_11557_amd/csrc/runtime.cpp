@@ -560,6 +560,77 @@ mwax_status mwax_read_channelised(mwax_plan p, void *d_out, int64_t max_spectra,
     return ok();
 }
 
+mwax_status mwax_beamform(mwax_plan p, const void *d_weights, int32_t n_beams, void *d_out, int64_t max_spectra,
+                          int64_t *n_spectra) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!d_weights || !d_out || !n_spectra) return fail(MWAX_E_INVAL, "null argument");
+    if (((uintptr_t)d_weights & 7) || ((uintptr_t)d_out & 7)) return fail(MWAX_E_INVAL, "weights and output must be 8-byte aligned");
+    if (n_beams < 1 || n_beams > 65535 * 64) return fail(MWAX_E_INVAL, "n_beams = %d out of range", n_beams);
+    if (!p->have_block) return fail(MWAX_E_STATE, "nothing has been channelised");
+    if (p->block_spectra > max_spectra)
+        return fail(MWAX_E_INVAL, "block holds %lld spectra, output room for %lld", (long long)p->block_spectra,
+                    (long long)max_spectra);
+    const int esize = p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4);
+    for (const Segment &s : p->segs) {
+        BeamArgs a{};
+        a.chan = p->chan;
+        a.NG = p->NG;
+        a.grp0 = s.grp0;
+        a.nframes = s.nframes;
+        a.m0 = s.frame0;
+        a.scales = p->xprec == MWAX_X_INT8 ? p->scales + (size_t)s.slot * 2 * p->L : nullptr;
+        a.post = p->xprec == MWAX_X_FP16 ? std::ldexp(1.0f, fp16_exponent(p->L)) : 1.0f;
+        a.n_in = p->n_in;
+        a.L = p->L;
+        a.nb = n_beams;
+        a.w = (const float2 *)d_weights;
+        a.out = (float2 *)d_out;
+        hipError_t e = launch_beamform(esize, a, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "beamformer launch");
+    }
+    *n_spectra = p->block_spectra;
+    return ok();
+}
+
+mwax_status mwax_beamform_incoherent(mwax_plan p, int32_t t_avg, int32_t f_avg, float *d_out, int64_t max_bins,
+                                     int64_t *n_time_bins) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!d_out || !n_time_bins) return fail(MWAX_E_INVAL, "null argument");
+    if ((uintptr_t)d_out & 3) return fail(MWAX_E_INVAL, "output must be 4-byte aligned");
+    if (!p->have_block) return fail(MWAX_E_STATE, "nothing has been channelised");
+    if (t_avg < 1 || p->block_spectra % t_avg != 0)
+        return fail(MWAX_E_INVAL, "t_avg = %d must divide the block's %lld spectra", t_avg, (long long)p->block_spectra);
+    if (f_avg < 1 || p->L % f_avg != 0) return fail(MWAX_E_INVAL, "f_avg = %d must divide L = %d", f_avg, p->L);
+    if ((int)p->segs.size() > kIncohMaxSeg)
+        return fail(MWAX_E_UNSUPPORTED, "block spans %zu integration segments, at most %d", p->segs.size(), kIncohMaxSeg);
+    const int64_t nj = p->block_spectra / t_avg;
+    if (nj * (p->L / f_avg) > max_bins)
+        return fail(MWAX_E_INVAL, "output needs %lld bins, room for %lld", (long long)(nj * (p->L / f_avg)),
+                    (long long)max_bins);
+    IncohArgs a{};
+    a.chan = p->chan;
+    a.NG = p->NG;
+    a.n_in = p->n_in;
+    a.L = p->L;
+    a.t_avg = t_avg;
+    a.f_avg = f_avg;
+    a.n_o = p->L / f_avg;
+    a.n_j = nj;
+    a.post = p->xprec == MWAX_X_FP16 ? std::ldexp(1.0f, fp16_exponent(p->L)) : 1.0f;
+    a.nseg = (int32_t)p->segs.size();
+    for (int k = 0; k < a.nseg; ++k) {
+        const Segment &s = p->segs[k];
+        a.seg_m0[k] = s.frame0;
+        a.seg_grp0[k] = s.grp0;
+        a.seg_scales[k] = p->xprec == MWAX_X_INT8 ? p->scales + (size_t)s.slot * 2 * p->L : nullptr;
+    }
+    a.out = d_out;
+    hipError_t e = launch_incoherent(p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4), a, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "incoherent beam launch");
+    *n_time_bins = nj;
+    return ok();
+}
+
 mwax_status mwax_correlate(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     if (!p->pending) return fail(MWAX_E_STATE, "no fresh channelised block to correlate");

@@ -25,7 +25,7 @@ EXPORTS = (
     "mwax_plan_derive", "mwax_plan_create", "mwax_plan_create_noalloc", "mwax_plan_destroy", "mwax_plan_get_dims",
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
-    "mwax_set_delays",
+    "mwax_set_delays", "mwax_beamform", "mwax_beamform_incoherent",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
@@ -120,6 +120,8 @@ def lib():
             "mwax_auto_scales": [vp],
             "mwax_get_scales": [vp, vp],
             "mwax_set_delays": [vp, vp, i64, i64, ctypes.c_double],
+            "mwax_beamform": [vp, vp, i32, vp, i64, P(i64)],
+            "mwax_beamform_incoherent": [vp, i32, i32, vp, i64, P(i64)],
             "mwax_reset": [vp],
             "mwax_sync": [vp],
             "mwax_set_timing": [vp, i32],
@@ -264,6 +266,33 @@ class Plan:
         n = ctypes.c_int64()
         _check(lib().mwax_read_channelised(self.h, ctypes.c_void_p(out.data_ptr()),
                                            self.dims.max_spectra, ctypes.byref(n)))
+        return out[: n.value]
+
+    def beamform(self, weights, out=None):
+        """Coherent beams of the last channelised block: weights complex64 [L][n_beams][n_inputs]
+        -> beams complex64 [n_spectra][L][n_beams]."""
+        t = self.torch
+        assert weights.is_cuda and weights.dtype == t.complex64 and weights.is_contiguous()
+        assert weights.dim() == 3 and weights.shape[0] == self.L and weights.shape[2] == self.n_in
+        nb = weights.shape[1]
+        if out is None:
+            out = t.empty((self.dims.max_spectra, self.L, nb), dtype=t.complex64, device="cuda")
+        assert out.is_cuda and out.dtype == t.complex64 and out.is_contiguous() and out.shape[1:] == (self.L, nb)
+        n = ctypes.c_int64()
+        _check(lib().mwax_beamform(self.h, ctypes.c_void_p(weights.data_ptr()), nb, ctypes.c_void_p(out.data_ptr()),
+                                   out.shape[0], ctypes.byref(n)))
+        return out[: n.value]
+
+    def beamform_incoherent(self, t_avg=1, f_avg=1, out=None):
+        """Incoherent beam of the last channelised block -> float32 [n_spectra/t_avg][L/f_avg][2]."""
+        t = self.torch
+        n_o = self.L // int(f_avg)
+        if out is None:
+            out = t.empty((self.dims.max_spectra // int(t_avg), n_o, 2), dtype=t.float32, device="cuda")
+        assert out.is_cuda and out.dtype == t.float32 and out.is_contiguous() and out.shape[1:] == (n_o, 2)
+        n = ctypes.c_int64()
+        _check(lib().mwax_beamform_incoherent(self.h, int(t_avg), int(f_avg), ctypes.c_void_p(out.data_ptr()),
+                                              out.shape[0] * n_o, ctypes.byref(n)))
         return out[: n.value]
 
     def correlate(self):

@@ -1,0 +1,152 @@
+"""GPU parity of the tied-array beamformer (Sec. 4.4) against the FP64 oracle.
+
+The beamformer reads the plan's channelised voltages, so each case is checked
+twice: on those exact voltages (read back, scales applied) the GPU's beams must
+match the oracle's sums to FP32 accumulation error (2e-6 of the beams' rms;
+incoherent powers to 1e-6 relative), and end to end from the voltages the FP32
+path must stay within 1e-5 of the oracle's FP64 chain.  A phased exact tone
+gives the closed form N A L to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2303_11557_amd import mwax  # noqa: E402
+from paper_2303_11557_amd.mwax import Plan, make_config  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    mwax.lib()
+    yield
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def weights(L, nb, n, seed):
+    u = synth.uniform(np.arange(L * nb * n, dtype=np.uint64), seed).reshape(L, nb, n)
+    g = synth.uniform(np.arange(L * nb * n, dtype=np.uint64), seed + 1).reshape(L, nb, n)
+    return ((0.5 + g) * np.exp(2j * np.pi * u)).astype(np.complex64)
+
+
+def spectra_of(p, prec, scales_per_spectrum=None):
+    """The plan's channelised block as complex128 [M][L][n], scales applied."""
+    x = p.read_channelised().cpu().numpy().astype(np.float64)
+    x = x[..., 0] + 1j * x[..., 1]
+    if prec == "fp16":
+        x = x * 2.0 ** ((int(np.ceil(np.log2(p.L))) + 1) // 2)
+    if scales_per_spectrum is not None:
+        x = x * scales_per_spectrum[:, :, None]
+    return x
+
+
+def rel_err(got, ref):
+    return np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8"])
+@pytest.mark.parametrize("n_tiles,L,M,nb", [(20, 16, 100, 70), (3, 128, 37, 5), (33, 2, 64, 64)])
+def test_coherent_beams(prec, n_tiles, L, M, nb):
+    n = 2 * n_tiles
+    v = synth.gaussian_volts(n, L * M, seed=900 + n + L, sources=[synth.Source(3.0, L // 4)], L=L)
+    w = weights(L, nb, n, seed=901 + nb)
+    with Plan(make_config(n_tiles, L=L, T=M, xprec=prec, max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        B = p.beamform(torch.from_numpy(w).cuda()).cpu().numpy().astype(np.complex128)
+        s = p.get_scales().cpu().numpy().astype(np.float64) if prec == "int8" else None
+        x = spectra_of(p, prec, None if s is None else np.broadcast_to(s, (M, L)))
+    assert B.shape == (M, L, nb)
+    e = rel_err(B, oracle.beamform(x, w))
+    log(f"beamform {prec} n={n} L={L} M={M} beams={nb}: {e:.3g} of rms on the plan's voltages")
+    assert e < 2e-6
+    if prec == "fp32":
+        e2 = rel_err(B, oracle.beamform(oracle.channelise(v, L), w))
+        assert e2 < 1e-5
+
+
+def test_phased_tone_closed_form():
+    # exact tone i^(s k0 4/L + p_n): conj(i^p_n) weights give N A L in the tone
+    # channel of every spectrum (to FP32 rounding), nothing elsewhere
+    n_tiles, L, M, A, k0 = 16, 16, 20, 30, 4
+    n = 2 * n_tiles
+    ph = np.arange(n) * 7 % 4
+    v = synth.tone_volts(n, L * M, L, k0, A, ph)
+    w = np.zeros((L, 2, n), np.complex64)
+    w[:, 0] = (1j ** ph).conj()
+    w[:, 1] = 1.0
+    c0 = (k0 + L // 2) % L
+    with Plan(make_config(n_tiles, L=L, T=M, xprec="fp32", max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        B = p.beamform(torch.from_numpy(w).cuda()).cpu().numpy()
+        inc = p.beamform_incoherent(M, L).cpu().numpy()
+    assert np.max(np.abs(B[:, c0, 0] - n * A * L)) <= 1e-5 * n * A * L
+    assert np.max(np.abs(np.delete(B, c0, axis=1))) < 1e-3 * A * L
+    assert inc.shape == (1, 1, 2)
+    assert inc[0, 0].sum() == pytest.approx(M * n * (A * L) ** 2, rel=1e-6)
+    assert np.abs(B[0, c0, 0]) ** 2 == pytest.approx(n * inc[0, 0].sum() / M, rel=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "int8"])
+def test_incoherent_beam(prec):
+    n_tiles, L, M = 9, 64, 48
+    n = 2 * n_tiles
+    v = synth.gaussian_volts(n, L * M, seed=910)
+    v[1::2] = (v[1::2].astype(np.int16) // 2).astype(np.int8)       # Y paths quieter
+    with Plan(make_config(n_tiles, L=L, T=M, xprec=prec, max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        got = p.beamform_incoherent(6, 8).cpu().numpy().astype(np.float64)
+        s = p.get_scales().cpu().numpy().astype(np.float64) if prec == "int8" else None
+        x = spectra_of(p, prec, None if s is None else np.broadcast_to(s, (M, L)))
+    want = oracle.incoherent(x, 6, 8)
+    assert got.shape == want.shape == (M // 6, L // 8, 2)
+    assert np.max(np.abs(got / want - 1)) < 1e-6
+    assert np.all(got[..., 0] > 2 * got[..., 1])
+
+
+def test_beams_across_integrations_use_their_scales():
+    # a block spanning three INT8 integrations (each with its own calibrated
+    # scales): beams and incoherent powers use every spectrum's own scale
+    n_tiles, L, T = 4, 32, 10
+    M = 3 * T
+    n = 2 * n_tiles
+    v = synth.gaussian_volts(n, L * M, seed=920)
+    v[:, L * T:2 * L * T] *= 2                                      # integration 1 twice as loud
+    w = weights(L, 3, n, seed=921)
+    with Plan(make_config(n_tiles, L=L, T=T, xprec="int8", max_samples=L * M)) as p:
+        p.channelise(torch.from_numpy(v).cuda())
+        B = p.beamform(torch.from_numpy(w).cuda()).cpu().numpy().astype(np.complex128)
+        inc = p.beamform_incoherent(5, 4).cpu().numpy().astype(np.float64)
+        q = p.read_channelised().cpu().numpy().astype(np.float64)
+        p.correlate()
+        _, sc = p.integrate_raw(3)
+        sc = sc.cpu().numpy().astype(np.float64)
+    assert sc.shape == (3, L) and sc[1, 0] > 1.5 * sc[0, 0]
+    x = (q[..., 0] + 1j * q[..., 1]) * np.repeat(sc, T, axis=0)[:, :, None]
+    assert rel_err(B, oracle.beamform(x, w)) < 2e-6
+    assert np.max(np.abs(inc / oracle.incoherent(x, 5, 4) - 1)) < 1e-6
+
+
+def test_beamform_errors():
+    with Plan(make_config(2, L=16, T=10, xprec="fp32", max_samples=160)) as p:
+        w = torch.zeros((16, 1, 4), dtype=torch.complex64, device="cuda")
+        with pytest.raises(mwax.MwaxError) as e:
+            p.beamform(w)
+        assert e.value.status == mwax.MWAX_E_STATE
+        p.channelise(torch.zeros((4, 160, 2), dtype=torch.int8, device="cuda"))
+        with pytest.raises(mwax.MwaxError) as e:
+            p.beamform_incoherent(3, 1)                              # 3 does not divide 10 spectra
+        assert e.value.status == mwax.MWAX_E_INVAL
+        with pytest.raises(mwax.MwaxError) as e:
+            p.beamform_incoherent(1, 3)                              # 3 does not divide 16 channels
+        assert e.value.status == mwax.MWAX_E_INVAL
+        assert p.beamform(w).shape == (10, 16, 1)

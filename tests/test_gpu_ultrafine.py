@@ -173,7 +173,12 @@ def test_fft6400_int8_end_to_end():
     log(f"fft6400 int8 end to end: max per-channel rel-Frobenius vs FP64 {err.max():.3g} "
         f"(oracle int8 chain {e_chain.max():.3g})")
     assert err.max() < 1.25 * e_chain.max() + 1e-4
-    assert rel_frob(got, v8).max() < 1e-4
+    # against the oracle's INT8 chain: channels whose codes all agree differ only
+    # by the scales (<= 1e-5 relative, squared in V); a code one step off at a
+    # rounding boundary moves its channel by more, and is allowed above
+    same = ~np.any(d != 0, axis=(0, 2, 3))
+    assert np.count_nonzero(same) > 0.99 * L
+    assert rel_frob(got, v8)[:, same].max() < 3e-5
 
 
 def test_fft6400_rejected_by_batches():
