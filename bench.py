@@ -168,11 +168,12 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "batch", "stream", "weights", "fscrunch", "ultrafine"],
+                    choices=["channel", "batch", "stream", "weights", "fscrunch", "ultrafine", "beamform"],
                     help="channel: one coarse channel, 256 tiles, 8 s (the headline metric); "
                          "batch: 24 uneven instances as one batch; stream: 24 channels streamed in 8 s blocks")
     ap.add_argument("--stream-rounds", type=int, default=15, help="8 s blocks per channel, flat out")
-    ap.add_argument("--stream-paced-rounds", type=int, default=4, help="8 s blocks per channel, real-time paced")
+    ap.add_argument("--stream-paced-rounds", type=int, default=15,
+                    help="8 s blocks per channel over the host link: flat out, then real-time paced (15 = 120 s)")
     ap.add_argument("--stream-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
     ap.add_argument("--ultra-modes", default="all", help="ultrafine: comma list of 40kHz_250ms,10kHz_1s,1kHz_8s")
     ap.add_argument("--steps", type=int, default=5)
@@ -585,6 +586,106 @@ def main_ultrafine(args):
     print(json.dumps(line), flush=True)
 
 
+# Beamformer workload: 256 tiles, one coarse channel, 1 s of voltages through
+# the INT8 F-engine at 128 channels (10 kHz), then BEAMS coherent beams (Sec.
+# 4.4: many pointings at the full coarse-channel bandwidth) and one incoherent
+# beam at 1 ms x 40 kHz resolution (t_avg 10 spectra, f_avg 4 channels).
+BEAMS = 32
+
+
+def main_beamform(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_11557_amd import mwax
+    from paper_2303_11557_amd.mwax import Plan, make_config
+
+    torch.cuda.set_device(0)
+    mwax.lib()
+    S = int(F_S)
+    n_in = 2 * N_TILES
+    M = S // L
+    volts = torch.empty((n_in, S, 2), dtype=torch.int8, device="cuda")
+    synth.device_volts(volts, seed=synth.MWAX_SEED + 11, sources=[synth.Source(3.0, 17)], L=L)
+    taus = synth.source_delays(n_in, synth.MWAX_SEED + 11)
+    nu = synth.NU_C + (np.arange(L) - L // 2) * F_S / L
+    # beam 0 phases every path up for the source's delays; the others point elsewhere
+    tau_b = np.stack([taus] + [taus * np.cos(0.3 * k) for k in range(1, BEAMS)])    # [BEAMS][n_in]
+    w = np.exp(2j * np.pi * nu[:, None, None] * tau_b[None, :, :]).astype(np.complex64)   # [L][BEAMS][n_in]
+    d_w = torch.from_numpy(w).cuda()
+    stream = torch.cuda.current_stream()
+    with Plan(make_config(N_TILES, L=L, T=M, xprec=args.xprec, max_samples=S)) as p:
+        beams = torch.empty((M, L, BEAMS), dtype=torch.complex64, device="cuda")
+        inc = torch.empty((M // 10, L // 4, 2), dtype=torch.float32, device="cuda")
+        p.channelise(volts)
+        p.correlate()
+        p.sync()
+
+        def step():
+            p.beamform(d_w, out=beams)
+            p.beamform_incoherent(10, 4, out=inc)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        for e in ev:
+            e[0].record(stream)
+            p.beamform(d_w, out=beams)
+            e[1].record(stream)
+            p.beamform_incoherent(10, 4, out=inc)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        b_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
+        i_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / len(ev)
+        g = beams[:, (17 + L // 2) % L, :].abs().pow(2).mean(0).cpu().numpy()
+    cmac = float(n_in) * BEAMS * M * L
+    flops = 8.0 * cmac
+    b_out = {"int8": 2, "fp16": 4, "fp32": 8}[args.xprec]
+    b_tf = flops / (b_ms / 1e3) / 1e12
+    i_bytes = n_in * S * b_out + (M // 10) * (L // 4) * 2 * 4
+    i_gbs = i_bytes / (i_ms / 1e3) / 1e9
+    peak = PEAK["fp32_vector_tflops"]         # the FP32 matrix-core peak is the same 157.3 TFLOP/s
+    line = {
+        "metric": "tied-array beamformer: coherent beams TFLOP/s and incoherent GB/s, 256 tiles",
+        "value": cmac / (b_ms / 1e3), "unit": "CMAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"256 tiles x 2 pols, 1 s of complex int8 sigma=8 voltages + 1 source, "
+                               f"{args.xprec} F-engine at 128 channels, {BEAMS} coherent beams, incoherent beam "
+                               "over 10 spectra x 4 channels", "beams": BEAMS, "spectra": M, "channels": L},
+        "roofline": {"kernel": "beamform_kernel", "bound": "mfma", "achieved": round(b_tf, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(b_tf / peak, 4), "traffic": None,
+                     "avg_launch_ms": round(b_ms, 4), "flops_per_launch": flops},
+        "incoherent": {"kernel": "incoherent_kernel", "bound": "hbm", "achieved": round(i_gbs, 1),
+                       "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(i_gbs / PEAK["hbm_gbs"], 4),
+                       "avg_launch_ms": round(i_ms, 4), "bytes_per_launch": i_bytes},
+        "phased_beam_gain": round(float(g[0] / np.median(g[1:])), 2),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle on a bounded sample: all inputs and beams, first spectra
+        n_spec = 256
+        with Plan(make_config(N_TILES, L=L, T=n_spec, xprec="fp32", max_samples=n_spec * L)) as p2:
+            p2.channelise(volts[:, : n_spec * L])
+            spec = p2.read_channelised().cpu().numpy().astype(np.float64)
+        spec = spec[..., 0] + 1j * spec[..., 1]
+        t0 = time.perf_counter()
+        oracle.beamform(spec, w)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": float(n_in) * BEAMS * n_spec * L / dt, "unit": "CMAC/s", "cores": 1,
+                                "kind": "oracle", "sample": f"all {n_in} inputs, {BEAMS} beams, {L} channels, "
+                                f"first {n_spec} spectra; FP64 sums; {dt:.1f} s wall"}
+    print(json.dumps(line), flush=True)
+
+
 def main_stream(args):
     """Streaming: 24 coarse channels x 256 tiles, continuous 8 s blocks, 2 s
     integrations on the device, int8 X-engine, admission by HBM budget.
@@ -627,6 +728,8 @@ def main_stream(args):
             t_start = s.now()
             nonlocal free
             for r in range(rounds):
+                print(f"stream {variant}{' paced' if paced else ''}: round {r + 1} of {rounds}", file=sys.stderr,
+                      flush=True)
                 t_arr = t_start + SECONDS * (r + 1) if paced else None
                 if paced:
                     while s.now() < t_arr:
@@ -700,6 +803,8 @@ def main():
         return main_fscrunch(args)
     if args.workload == "ultrafine":
         return main_ultrafine(args)
+    if args.workload == "beamform":
+        return main_beamform(args)
 
     import torch
 

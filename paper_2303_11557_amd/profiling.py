@@ -3,6 +3,9 @@
     python -m paper_2303_11557_amd.profiling stats <kernel_stats.csv>
         per-kernel dispatch count and average / min / max duration (markdown)
 
+    python -m paper_2303_11557_amd.profiling counters <counter_collection.csv> ...
+        average value per dispatch of each collected counter, per hot-path kernel
+
     python -m paper_2303_11557_amd.profiling traffic <fetch.csv> <write.csv> [--out traffic.json]
         HBM bytes per dispatch of each hot-path kernel from FETCH_SIZE and
         WRITE_SIZE counter runs.  Both counters are scaled by what they read for
@@ -27,6 +30,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {
     "fengine": os.path.join(HERE, "csrc", "fengine.hip"),
+    "fft6400": os.path.join(HERE, "csrc", "fft6400.hip"),
+    "beamform": os.path.join(HERE, "csrc", "beamform.hip"),
     "xengine": os.path.join(HERE, "csrc", "xengine.hip"),
     "pack": os.path.join(HERE, "csrc", "pack.hip"),
     "weights": os.path.join(HERE, "csrc", "weights.hip"),
@@ -57,10 +62,21 @@ def short_name(name):
 def kernel_key(name):
     """Stable key of a hot-path kernel ('fengine_int8', 'xengine_int8', ...), or None."""
     s = short_name(name)
-    m = re.match(r"fengine_(batch_)?kernel<(\d+), (\d), (false|true)>", s)
+    m = re.match(r"fengine_(batch_)?kernel<(\d+), (\d), (false|true)(, (false|true))?>", s)
     if m:
         return (f"fengine_{'batch_' if m.group(1) else ''}{PREC[m.group(3)]}"
-                + ("_stats" if m.group(4) == "true" else ""))
+                + ("_stats" if m.group(4) == "true" else "") + ("_delay" if m.group(6) == "true" else ""))
+    m = re.match(r"fft6400_kernel<(\d), (false|true), (false|true)>", s)
+    if m:
+        return (f"fft6400_{PREC[m.group(1)]}" + ("_stats" if m.group(2) == "true" else "")
+                + ("_delay" if m.group(3) == "true" else ""))
+    m = re.match(r"corner_turn_kernel<(\d)>", s)
+    if m:
+        return "fft6400_corner_turn_" + {"1": "int8", "2": "fp16", "4": "fp32"}[m.group(1)]
+    if s.startswith("beamform_kernel"):
+        return "beamform_coherent"
+    if s.startswith("incoherent_kernel"):
+        return "beamform_incoherent"
     m = re.match(r"xengine_(mfma|batch)<(\d)>", s)
     if m:
         return f"xengine_{'batch_' if m.group(1) == 'batch' else ''}{PREC[m.group(2)]}"
@@ -130,6 +146,30 @@ def traffic(fetch_csv, write_csv, copy_bytes):
     return out
 
 
+def counters_table(paths):
+    """Average value per dispatch of every counter in the given counter-collection
+    CSVs, per hot-path kernel (markdown)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    names = []
+    for path in paths:
+        vals = collections.defaultdict(float)
+        for r in csv.DictReader(open(path)):
+            vals[(int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"])] += float(r["Counter_Value"])
+        for (d, n, c), v in vals.items():
+            k = kernel_key(n)
+            if k:
+                per[k][c].append(v)
+                if c not in names:
+                    names.append(c)
+    lines = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for k in sorted(per):
+        cols = [per[k][c] for c in names]
+        nd = max(len(x) for x in cols if x)
+        lines.append(f"| {k} | {nd} | " + " | ".join(
+            f"{sum(x) / len(x):.4g}" if x else "-" for x in cols) + " |")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -140,9 +180,13 @@ def main(argv=None):
     t.add_argument("write_csv")
     t.add_argument("--copy-bytes", type=float, default=float(4 << 30))
     t.add_argument("--out")
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv))
+    elif a.cmd == "counters":
+        print(counters_table(a.csv))
     else:
         tr = traffic(a.fetch_csv, a.write_csv, a.copy_bytes)
         txt = json.dumps(tr, indent=1, sort_keys=True)
