@@ -175,6 +175,7 @@ def parse():
     ap.add_argument("--stream-paced-rounds", type=int, default=15,
                     help="8 s blocks per channel over the host link: flat out, then real-time paced (15 = 120 s)")
     ap.add_argument("--stream-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
+    ap.add_argument("--fft-len", type=int, default=L, help="channel workload: FFT length (default 128)")
     ap.add_argument("--ultra-modes", default="all", help="ultrafine: comma list of 40kHz_250ms,10kHz_1s,1kHz_8s")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -480,7 +481,6 @@ def main_ultrafine(args):
     torch.cuda.set_device(0)
     mwax.lib()
     S = int(SECONDS * F_S)
-    call = int(F_S)
     n_in = 2 * N_TILES
     P = n_in * (n_in + 1) // 2
     cmac = P * S
@@ -488,32 +488,25 @@ def main_ultrafine(args):
     synth.device_volts(volts, seed=synth.MWAX_SEED + 2,
                        sources=[synth.Source(2.0, -370), synth.Source(3.0, 50), synth.Source(4.0, 2010)], L=ULTRA_L)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
     modes = {}
     for name, (F, tau) in ULTRA_MODES.items():
         if args.ultra_modes != "all" and name not in args.ultra_modes.split(","):
             continue
+        # calls of 1 s, or of the whole integration when it is longer (one
+        # X-engine flush per integration); every completed integration is
+        # emitted already averaged to the output width
+        call = int(max(1.0, tau) * F_S)
         cfg = make_config(N_TILES, L=ULTRA_L, int_time_s=tau, xprec=args.xprec, max_samples=call)
         n_ints = int(round(SECONDS / tau))
         with Plan(cfg) as p:
-            vis = torch.empty((1, ULTRA_L, P), dtype=torch.complex64, device="cuda")
             out = torch.empty((n_ints, ULTRA_L // F, P), dtype=torch.complex64, device="cuda")
-            ev_f = []
 
-            def step(timed=False):
+            def step():
                 j = 0
                 for off in range(0, S, call):
                     p.channelise(volts[:, off:off + call])
                     p.correlate()
-                    while p.integrate(1, out=vis).shape[0] == 1:
-                        if timed:
-                            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                            e0.record(stream)
-                        mwax.fscrunch(vis, F, out=out[j:j + 1], stream=stream)
-                        if timed:
-                            e1.record(stream)
-                            ev_f.append((e0, e1))
-                        j += 1
+                    j += p.integrate_averaged(F, n_ints - j, out=out[j:]).shape[0]
                 return j
 
             for _ in range(args.warmup):
@@ -529,11 +522,10 @@ def main_ultrafine(args):
             p.set_timing(True)
             for fam in range(4):
                 p.kernel_time(fam)
-            step(timed=True)
+            step()
             p.sync()
             fam = {name_: p.kernel_time(i) for i, name_ in enumerate(("fengine", "xengine", "pack", "calib"))}
             p.set_timing(False)
-            fs_ms = sum(a.elapsed_time(b) for a, b in ev_f)
         b_out = {"int8": 2, "fp16": 4, "fp32": 8}[args.xprec]
         x_peak = {"int8": PEAK["int8_tops"], "fp16": PEAK["fp16_tflops"], "fp32": PEAK["fp32_vector_tflops"]}[args.xprec]
         f_ms, f_n = fam["fengine"]
@@ -541,8 +533,8 @@ def main_ultrafine(args):
         p_ms, p_n = fam["pack"]
         f_bytes = n_in * S * (2 + b_out)               # algorithmic: voltages in, channel-major spectra out
         x_ops = 8.0 * cmac
-        pack_bytes = n_ints * ULTRA_L * P * (8 + 8)    # int32-pair integrators in, complex64 out
-        fs_bytes = n_ints * (ULTRA_L + ULTRA_L // F) * P * 8
+        integ_b = 8 if args.xprec == "int8" and tau * F_S / ULTRA_L <= 65536 else 16
+        avg_bytes = n_ints * (ULTRA_L * P * integ_b + (ULTRA_L // F) * P * 8)   # integrators in, averages out
         kern = {
             "fengine": {"bound": "hbm", "ms": round(f_ms, 3), "launches": f_n, "bytes": f_bytes,
                         "achieved": round(f_bytes / (f_ms / 1e3) / 1e9, 1), "unit": "GB/s",
@@ -550,16 +542,14 @@ def main_ultrafine(args):
             "xengine": {"bound": "mfma", "ms": round(x_ms, 3), "launches": x_n, "ops": x_ops,
                         "achieved": round(x_ops / (x_ms / 1e3) / 1e12, 2), "unit": "TFLOP/s",
                         "frac": round(x_ops / (x_ms / 1e3) / 1e12 / x_peak, 4)},
-            "pack": {"bound": "hbm", "ms": round(p_ms, 3), "launches": p_n, "bytes": pack_bytes,
-                     "achieved": round(pack_bytes / (p_ms / 1e3) / 1e9, 1), "unit": "GB/s",
-                     "frac": round(pack_bytes / (p_ms / 1e3) / 1e9 / PEAK["hbm_gbs"], 4)},
-            "fscrunch": {"bound": "hbm", "ms": round(fs_ms, 3), "launches": len(ev_f), "bytes": fs_bytes,
-                         "achieved": round(fs_bytes / (fs_ms / 1e3) / 1e9, 1), "unit": "GB/s",
-                         "frac": round(fs_bytes / (fs_ms / 1e3) / 1e9 / PEAK["hbm_gbs"], 4)},
+            "integrate_averaged": {"bound": "hbm", "ms": round(p_ms, 3), "launches": p_n, "bytes": avg_bytes,
+                                   "achieved": round(avg_bytes / (p_ms / 1e3) / 1e9, 1), "unit": "GB/s",
+                                   "frac": round(avg_bytes / (p_ms / 1e3) / 1e9 / PEAK["hbm_gbs"], 4)},
             "calib_ms": round(fam["calib"][0], 3),
         }
-        dom = max(("fengine", "xengine", "pack", "fscrunch"), key=lambda k: kern[k]["ms"])
-        modes[name] = {"fscrunch": F, "int_time_s": tau, "integrations": n_ints, "output_channels": ULTRA_L // F,
+        dom = max(("fengine", "xengine", "integrate_averaged"), key=lambda k: kern[k]["ms"])
+        modes[name] = {"fscrunch": F, "int_time_s": tau, "call_s": call / F_S, "integrations": n_ints,
+                       "output_channels": ULTRA_L // F,
                        "ms_per_8s": round(ms, 3), "rtf_per_channel": round(SECONDS / (ms / 1e3), 2),
                        "rtf_24_channels": round(SECONDS / (ms / 1e3) / 24.0, 3),
                        "cmac_per_s": cmac / (ms / 1e3), "dominant": dom, "kernels": kern}
@@ -574,8 +564,9 @@ def main_ultrafine(args):
         "ms_per_step": head["ms_per_8s"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.xprec, "data": "synthetic",
         "config": {"workload": "256 tiles x 2 pols, 1 coarse channel, 8 s block of complex int8 sigma=8 "
-                               "voltages + 3 sources, 6,400-pt FFT (200 Hz), 1 s plan calls, each integration "
-                               "averaged to the output width (modes: 40 kHz/250 ms, 10 kHz/1 s, 1 kHz/8 s)",
+                               "voltages + 3 sources, 6,400-pt FFT (200 Hz), plan calls of max(1 s, integration), "
+                               "each integration emitted averaged to the output width (modes: 40 kHz/250 ms, "
+                               "10 kHz/1 s, 1 kHz/8 s)",
                    "fft_len": ULTRA_L, "samples": S, "cmac_per_8s": cmac},
         "roofline": {"kernel": head["dominant"], "bound": dk["bound"], "achieved": dk["achieved"],
                      "peak": PEAK["hbm_gbs"] if dk["bound"] == "hbm" else PEAK[{"int8": "int8_tops", "fp16": "fp16_tflops", "fp32": "fp32_vector_tflops"}[args.xprec]],
@@ -814,6 +805,7 @@ def main():
 
     torch.cuda.set_device(0)
     mwax.lib()
+    L = args.fft_len
     S = int(SECONDS * F_S)
     n_in = 2 * N_TILES
     T = S // L
@@ -937,7 +929,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "256 tiles x 2 pols, 1 coarse channel, 8 s (10.24 M samples) complex int8 "
-                        "Gaussian sigma=8 + 3 point sources, 128-pt FFT, one 8 s integration, "
+                        f"Gaussian sigma=8 + 3 point sources, {L}-pt FFT, one 8 s integration, "
                         f"{args.xprec} X-engine",
             "n_inputs": n_in, "samples": S, "fft_len": L, "spectra_per_integration": T,
             "pairs": P, "cmac_per_step": cmac_per_step,

@@ -230,6 +230,19 @@ mwax_status mwax_correlate(mwax_plan p);
 mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *n_emitted,
                            int32_t order);
 
+/* Like mwax_integrate in CHAN_TRI order, with the channel averaging of Sec. 2.6
+ * (the rule of mwax_fscrunch: centre-symmetric output channels of F fine
+ * channels, half-weight shared boundaries for even F, DC left out of the centre
+ * channel) done in the same pass over the integrators: d_vis receives
+ * [max_ints][L / fscrunch][P] complex64, means of the scaled sums in FP64
+ * rounded once.  d_weights, if not NULL, is [max_ints][P] float32 occupancy
+ * weights (mwax_vis_weights) of the emitted integrations, dividing each pair's
+ * means where positive.  For L = 6400 this is the paper's output path: the
+ * 6,400-channel visibilities are never written.  MWAX_E_INVAL if fscrunch does
+ * not divide L. */
+mwax_status mwax_integrate_averaged(mwax_plan p, int32_t fscrunch, const float *d_weights, void *d_vis,
+                                    int32_t max_ints, int32_t *n_emitted);
+
 /* INT8 plans only: like mwax_integrate in CHAN_TRI order but emits the exact
  * int64 sums, d_vis = [max_ints][L][P][2] int64 (re, im), and, if d_scales is
  * not NULL, the per-channel scales s_c used, [max_ints][L] float32.

@@ -23,8 +23,6 @@ namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr int kBT = 64;     // beams per workgroup tile
-constexpr int kMT = 64;     // spectra per workgroup tile
 constexpr int kKC = 32;     // inputs per LDS stage
 constexpr int kWP = kKC + 1;   // float2 pitch of a beam's weights in LDS
 
@@ -39,9 +37,13 @@ __device__ __forceinline__ float2 row_value(const uint8_t *row, int t) {
     else return make_float2(*reinterpret_cast<const float *>(row + re), *reinterpret_cast<const float *>(row + im));
 }
 
-template <int ES>
+// WB waves along the beams, 4 / WB along the spectra: a tile of 32 WB beams x
+// 128 / WB spectra (WB = 1 when a launch has at most 32 beams, so that no wave
+// multiplies empty beams).
+template <int ES, int WB>
 __global__ __launch_bounds__(256) void beamform_kernel(BeamArgs a) {
     constexpr int G = 16 / ES;
+    constexpr int kBT = 32 * WB, kMT = 128 / WB;
     // one LDS block: the stage (weights [beam][input], voltages [input][spectrum])
     // and, after the K loop, the output tile [spectrum][beam] (pitch kBT + 1)
     constexpr int kStage = kBT * kWP + kKC * kMT, kOut = kMT * (kBT + 1);
@@ -50,19 +52,21 @@ __global__ __launch_bounds__(256) void beamform_kernel(BeamArgs a) {
     const int c = blockIdx.z;
     const int m0 = blockIdx.x * kMT, b0 = blockIdx.y * kBT;
     const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, l32 = lane & 31;
-    const int wave = tid >> 6, wb = wave >> 1, wm = wave & 1;
+    const int wave = tid >> 6, wb = wave / (4 / WB), wm = wave % (4 / WB);
     v16f acc_r, acc_i;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc_r[r] = acc_i[r] = 0.0f;
 
     for (int n0 = 0; n0 < a.n_in; n0 += kKC) {
         __syncthreads();   // the previous stage has been read
-        // weights: thread -> beam tid / 4, inputs (tid % 4) * 8 .. + 7
+        // weights: thread -> beam tid / 4, inputs (tid % 4) * 8 .. + 7 (WB = 2), or
+        // beam tid / 8, inputs (tid % 8) * 4 .. + 3 (WB = 1)
         {
-            const int bl = tid >> 2, nl0 = (tid & 3) * 8;
+            constexpr int PER = kBT * kKC / 256;
+            const int bl = tid / (kKC / PER), nl0 = (tid % (kKC / PER)) * PER;
             const int b = b0 + bl;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
+            for (int e = 0; e < PER; ++e) {
                 const int n = n0 + nl0 + e;
                 float2 w = make_float2(0.0f, 0.0f);
                 if (b < a.nb && n < a.n_in) w = a.w[((int64_t)c * a.nb + b) * a.n_in + n];
@@ -164,16 +168,22 @@ __global__ __launch_bounds__(256) void incoherent_kernel(IncohArgs a) {
 
 }  // namespace
 
-hipError_t launch_beamform(int esize, const BeamArgs &a, hipStream_t s) {
-    if (a.nframes <= 0 || a.nb <= 0) return hipSuccess;
+template <int WB>
+hipError_t launch_beamform_wb(int esize, const BeamArgs &a, hipStream_t s) {
+    constexpr int kBT = 32 * WB, kMT = 128 / WB;
     const dim3 grid((unsigned)((a.nframes + kMT - 1) / kMT), (unsigned)((a.nb + kBT - 1) / kBT), (unsigned)a.L);
     switch (esize) {
-        case 1: hipLaunchKernelGGL(beamform_kernel<1>, grid, dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(beamform_kernel<2>, grid, dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(beamform_kernel<4>, grid, dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((beamform_kernel<1, WB>), grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((beamform_kernel<2, WB>), grid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((beamform_kernel<4, WB>), grid, dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_beamform(int esize, const BeamArgs &a, hipStream_t s) {
+    if (a.nframes <= 0 || a.nb <= 0) return hipSuccess;
+    return a.nb <= 32 ? launch_beamform_wb<1>(esize, a, s) : launch_beamform_wb<2>(esize, a, s);
 }
 
 hipError_t launch_incoherent(int esize, const IncohArgs &a, hipStream_t s) {

@@ -279,12 +279,14 @@ struct PackArgs {
     double post;            // FP16/FP32: multiply by this (2^(2e) or 1)
     void *out;              // complex64 or int64 output of this integration
     float *scales_out;      // raw mode: copy of s_c, may be NULL
-    int32_t order;          // mwax_order; 2 = raw int64
+    int32_t order;          // mwax_order; 2 = raw int64; 3 = averaged by F (CHAN_TRI)
     int32_t clear;          // zero the integrators after reading them
     int32_t i32;            // INT8 integrators are int32 pairs (else int64)
     int32_t L;
     int32_t n_in;
     int64_t P;
+    int32_t F;              // order 3: channels averaged into one (Sec. 2.6)
+    const float *avg_w;     // order 3: occupancy weights [P] of this integration, or NULL
 };
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);

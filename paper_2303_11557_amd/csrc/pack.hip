@@ -75,6 +75,52 @@ __global__ void pack_tri_kernel(PackArgs a) {
     }
 }
 
+// Emission with channel averaging in the same pass (Sec. 2.6): output channel o
+// of N = L / F holds the weighted mean of its fine channels' scaled integrator
+// values (the rule of average.hip: offsets |d| <= F/2 around its centre, the
+// outermost two at weight 1/2 for even F, DC left out of the centre channel),
+// optionally divided by the pair's occupancy weight; FP64 sums, one rounding.
+// Reading the integrators once replaces a pack to 6,400-channel visibilities
+// and a second pass over them.
+__global__ void pack_avg_kernel(PackArgs a) {
+    const int N = a.L / a.F, oc = N / 2, half = a.F / 2;
+    const bool even = (a.F & 1) == 0;
+    const int64_t total = (int64_t)N * a.P;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(t / a.P);
+        const int64_t p = t - (int64_t)o * a.P;
+        const int64_t n1 = a.is_int ? tri_row(p) : 0;
+        const bool centre = a.F > 1 && o == oc;
+        double re = 0.0, im = 0.0, wsum = 0.0;
+        for (int d = -half; d <= half; ++d) {
+            if (centre && d == 0) continue;
+            const double w = even && (d == -half || d == half) ? 0.5 : 1.0;
+            const int c = ((a.L / 2 + (o - oc) * a.F + d) % a.L + a.L) % a.L;
+            double vr, vi;
+            if (a.is_int) {
+                const longlong2 v = int_vis(a, c, n1, p);
+                const double sc = (double)a.scales[c];
+                vr = (double)v.x * sc * sc;
+                vi = (double)v.y * sc * sc;
+            } else {
+                const double2 v = reinterpret_cast<const double2 *>(a.integ)[(int64_t)c * a.P + p];
+                vr = v.x * a.post;
+                vi = v.y * a.post;
+            }
+            re += w * vr;
+            im += w * vi;
+            wsum += w;
+        }
+        double div = wsum;
+        if (a.avg_w) {
+            const double wp = (double)a.avg_w[p];
+            if (wp > 0.0) div *= wp;
+        }
+        reinterpret_cast<float2 *>(a.out)[t] = make_float2((float)(re / div), (float)(im / div));
+    }
+}
+
 // gather pass of the tile-baseline order (integrators cleared afterwards)
 __global__ void pack_tilebl_kernel(PackArgs a) {
     const int64_t nt = a.n_in / 2;
@@ -129,6 +175,14 @@ static size_t clear_bytes(const PackArgs &a) {
 }
 
 hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
+    if (a.order == 3) {
+        if (a.F < 1 || a.L % a.F != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(pack_avg_kernel, dim3(grid_for((int64_t)(a.L / a.F) * a.P)), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !a.clear) return e;
+        return a.is_int ? launch_fill_zero(a.integ, clear_bytes(a), s)
+                        : launch_fill_zero(a.integ, (size_t)a.L * a.P * 16, s);
+    }
     if (a.order == MWAX_ORDER_TILE_BL) {
         const int64_t nt = a.n_in / 2;
         const int64_t total = nt * (nt + 1) / 2 * a.L * 4;

@@ -363,6 +363,10 @@ mwax_status create_plan(const mwax_config *cfg, void *hip_stream, mwax_plan *out
     p->slot_bytes = (size_t)integ_slot_bytes(p->xprec, p->T, p->L, p->P);
     p->slot_owner.assign(p->nslots, -1);
     p->slot_count.assign(p->nslots, 0);
+    // 6,400 channels: an integration's first X-engine flush overwrites its slot,
+    // so slots are not cleared when emitted (mwax_correlate clears one itself
+    // before a launch that would add into it)
+    if (p->L == kUltraFineL) p->clear_on_emit = false;
 
     // workspace buffers, in order
     const size_t esize = p->xprec == MWAX_X_INT8 ? 1 : (p->xprec == MWAX_X_FP16 ? 2 : 4);
@@ -650,10 +654,12 @@ mwax_status mwax_correlate(mwax_plan p) {
 }
 
 static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_ints, int32_t *n_emitted,
-                        int32_t order) {
+                        int32_t order, int32_t F = 1, const float *avg_w = nullptr) {
     int32_t n = 0;
     const double post = p->xprec == MWAX_X_FP16 ? std::ldexp(1.0, 2 * fp16_exponent(p->L)) : 1.0;
-    const size_t per_int = order == MWAX_ORDER_TILE_BL ? (size_t)p->d.n_baselines * p->L * 4 : (size_t)p->L * p->P;
+    const size_t per_int = order == MWAX_ORDER_TILE_BL ? (size_t)p->d.n_baselines * p->L * 4
+                           : order == 3                ? (size_t)(p->L / F) * p->P
+                                                       : (size_t)p->L * p->P;
     const size_t esz = order == 2 ? 16 : 8;
     while (n < max_ints) {
         const int64_t j = p->next_emit;
@@ -672,6 +678,8 @@ static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_i
         a.L = p->L;
         a.n_in = p->n_in;
         a.P = p->P;
+        a.F = F;
+        a.avg_w = avg_w ? avg_w + (size_t)n * p->P : nullptr;
         hipError_t e = timed(p, 2, [&] { return launch_pack(a, p->stream); });
         if (e != hipSuccess) return hip_fail(e, "pack launch");
         p->slot_owner[slot] = -1;
@@ -691,6 +699,19 @@ mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *
     if (order != MWAX_ORDER_CHAN_TRI && order != MWAX_ORDER_TILE_BL) return fail(MWAX_E_INVAL, "unknown order %d", order);
     if (((uintptr_t)d_vis & 7) != 0) return fail(MWAX_E_INVAL, "output must be 8-byte aligned");
     return emit(p, d_vis, nullptr, max_ints, n_emitted, order);
+}
+
+mwax_status mwax_integrate_averaged(mwax_plan p, int32_t fscrunch, const float *d_weights, void *d_vis,
+                                    int32_t max_ints, int32_t *n_emitted) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (!n_emitted) return fail(MWAX_E_INVAL, "null n_emitted");
+    *n_emitted = 0;
+    if (fscrunch < 1 || p->L % fscrunch != 0)
+        return fail(MWAX_E_INVAL, "fscrunch = %d must divide L = %d", fscrunch, p->L);
+    if (max_ints < 0 || (max_ints > 0 && !d_vis)) return fail(MWAX_E_INVAL, "bad output buffer");
+    if (((uintptr_t)d_vis & 7) != 0 || ((uintptr_t)d_weights & 3) != 0)
+        return fail(MWAX_E_INVAL, "output must be 8-byte and weights 4-byte aligned");
+    return emit(p, d_vis, nullptr, max_ints, n_emitted, 3, fscrunch, d_weights);
 }
 
 mwax_status mwax_integrate_raw_i64(mwax_plan p, int64_t *d_vis, float *d_scales, int32_t max_ints,

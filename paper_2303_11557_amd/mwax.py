@@ -25,7 +25,7 @@ EXPORTS = (
     "mwax_plan_derive", "mwax_plan_create", "mwax_plan_create_noalloc", "mwax_plan_destroy", "mwax_plan_get_dims",
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
-    "mwax_set_delays", "mwax_beamform", "mwax_beamform_incoherent",
+    "mwax_set_delays", "mwax_beamform", "mwax_beamform_incoherent", "mwax_integrate_averaged",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
@@ -121,6 +121,7 @@ def lib():
             "mwax_get_scales": [vp, vp],
             "mwax_set_delays": [vp, vp, i64, i64, ctypes.c_double],
             "mwax_beamform": [vp, vp, i32, vp, i64, P(i64)],
+            "mwax_integrate_averaged": [vp, i32, vp, vp, i32, P(i32)],
             "mwax_beamform_incoherent": [vp, i32, i32, vp, i64, P(i64)],
             "mwax_reset": [vp],
             "mwax_sync": [vp],
@@ -311,6 +312,25 @@ class Plan:
         n = ctypes.c_int32()
         _check(lib().mwax_integrate(self.h, ctypes.c_void_p(out.data_ptr()), max_ints,
                                     ctypes.byref(n), o))
+        return out[: n.value]
+
+    def integrate_averaged(self, fscrunch, max_ints=1, weights=None, out=None):
+        """Emit completed integrations averaged by fscrunch (Sec. 2.6) in the same
+        pass -> complex64 [n][L / fscrunch][P]; weights: [max_ints][P] float32 or None."""
+        t = self.torch
+        F = int(fscrunch)
+        if out is None:
+            out = t.empty((max_ints, self.L // F, self.P), dtype=t.complex64, device="cuda")
+        assert out.is_cuda and out.dtype == t.complex64 and out.is_contiguous()
+        assert out.shape[1:] == (self.L // F, self.P) and out.shape[0] >= max_ints
+        wp = ctypes.c_void_p()
+        if weights is not None:
+            assert weights.is_cuda and weights.dtype == t.float32 and weights.is_contiguous()
+            assert weights.shape[1] == self.P and weights.shape[0] >= max_ints
+            wp = ctypes.c_void_p(weights.data_ptr())
+        n = ctypes.c_int32()
+        _check(lib().mwax_integrate_averaged(self.h, F, wp, ctypes.c_void_p(out.data_ptr()), max_ints,
+                                             ctypes.byref(n)))
         return out[: n.value]
 
     def integrate_raw(self, max_ints=1):

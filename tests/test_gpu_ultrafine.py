@@ -185,3 +185,47 @@ def test_fft6400_rejected_by_batches():
     with pytest.raises(mwax.MwaxError) as e:
         mwax.Batch([make_config(2, L=L, T=10, xprec="int8", max_samples=10 * L)])
     assert e.value.status == mwax.MWAX_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,Lc,F", [("fp32", L, 200), ("fp32", L, 5), ("int8", L, 50), ("int8", 1024, 8),
+                                       ("fp16", 256, 4)])
+def test_integrate_averaged_equals_averaging_of_the_visibilities(prec, Lc, F):
+    # emission with the averaging of Sec. 2.6 in the same pass over the
+    # integrators: equal (to one FP32 rounding of an FP64 mean) to the oracle's
+    # averaging of the plan's own exact visibilities, with and without weights
+    n_tiles = 3
+    n = 2 * n_tiles
+    T = 12 if Lc == L else 40
+    S = 2 * T * Lc
+    v = synth.gaussian_volts(n, S, seed=650 + Lc + F, sources=[synth.Source(4.0, Lc // 5)], L=Lc)
+    d = torch.from_numpy(v).cuda()
+    w = np.full((2, n * (n + 1) // 2), 0.75, np.float32)
+    w[:, 3] = 0.0
+    cfg = make_config(n_tiles, L=Lc, T=T, xprec=prec, max_samples=S)
+    with Plan(cfg) as p:
+        p.channelise(d)
+        p.correlate()
+        if prec == "int8":
+            raw, sc = p.integrate_raw(2)
+            exact = (raw.cpu().numpy()[..., 0] + 1j * raw.cpu().numpy()[..., 1]) * \
+                (sc.cpu().numpy().astype(np.float64) ** 2)[:, :, None]
+        else:
+            exact = p.integrate(2).cpu().numpy().astype(np.complex128)
+    outs = {}
+    for weighted in (False, True):
+        with Plan(cfg) as p:
+            p.channelise(d)
+            p.correlate()
+            wt = torch.from_numpy(w).cuda() if weighted else None
+            outs[weighted] = p.integrate_averaged(F, 2, weights=wt).cpu().numpy().astype(np.complex128)
+    want = oracle.fscrunch(exact, F)
+    assert outs[False].shape == want.shape == (2, Lc // F, n * (n + 1) // 2)
+    if prec == "int8":
+        # the exact sums, averaged in FP64 and rounded once to FP32
+        assert np.all(np.abs(outs[False] - want) <= 2.0 ** -23 * np.abs(want) + 1e-30)
+    else:
+        # the plan's FP32 visibilities were rounded once more before the oracle averaged them
+        assert np.max(rel_frob(outs[False], want)) < 1e-6
+    ww = oracle.apply_weights(want, w.astype(np.float64))
+    assert np.max(rel_frob(outs[True], ww)) < 1e-6
+    assert np.array_equal(outs[True][:, :, 3], outs[False][:, :, 3])
