@@ -15,6 +15,7 @@
 // quantised outputs are written to an LDS image of the workgroup's output rows,
 // which is then stored with coalesced 16-byte writes.
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_common.h"
 #include "mwax_internal.h"
@@ -27,10 +28,10 @@ using namespace fft;
 // Two-pass split L = L1 * L2 over an FFT group of L2 lanes.  Pass 2 (length L2)
 // is done by each lane on U columns when L2 <= L1.  INT8 at L >= 512 keeps 16
 // points per lane (L2 = 32 or 64 > L1 = 16): each pass-2 transform is shared by
-// P = L2 / 16 neighbouring lanes, an in-lane 16-point DFT and then log2 P
-// radix-2 stages across the lanes (see fengine_body).  Measured: 1.2x (L = 1024)
-// and 1.1x (L = 512) over 32 points per lane for INT8, 0.9x for binary16, whose
-// 32-point kernels do not spill.
+// P = L2 / 16 neighbouring lanes, an in-lane 16-point DFT, a second exchange and
+// in-lane P-point DFTs (see fengine_body).  Measured: 1.2x (L = 1024) and 1.1x
+// (L = 512) over 32 points per lane for INT8, 0.9x for binary16, whose 32-point
+// kernels do not spill.
 template <int L, int XP>
 struct FftShape {
     static constexpr bool kLaneSplit = XP == MWAX_X_INT8 && L >= 512;
@@ -53,11 +54,12 @@ struct PrecTraits<MWAX_X_FP32> { static constexpr int G = 4, ES = 4; };
 
 // Channel of output slot i of lane r (see the kernel comment): bin
 // k = (r U + u) + L1 k2 with i = u L2 + k2; with P lanes per pass-2 transform,
-// lane r = k1 P + h holds k = k1 + L1 (i + L1 bitrev_P(h)).  Channel (k + L/2) mod L.
+// lane r = k1 P + g holds k = k1 + L1 (g + P j + L1 q) in slot i = j P + q.
+// Channel (k + L/2) mod L.
 template <int L, int XP>
 __device__ __forceinline__ int bin_of(int r, int i) {
     using SH = FftShape<L, XP>;
-    if constexpr (SH::P > 1) return r / SH::P + SH::L1 * (i + SH::L1 * bitrev<SH::P>(r % SH::P));
+    if constexpr (SH::P > 1) return r / SH::P + SH::L1 * (r % SH::P + SH::P * (i / SH::P) + SH::L1 * (i % SH::P));
     else if constexpr (SH::L2 > 1) return (r * SH::U + i / SH::L2) + SH::L1 * (i % SH::L2);
     else return i;
 }
@@ -73,19 +75,6 @@ __device__ __forceinline__ float2 delay_gain(int ks, float alpha, float phi) {
     float sn, cs;
     sincospif(-2.0f * fmaf((float)ks, alpha, phi), &sn, &cs);
     return make_float2(cs, sn);
-}
-
-// One radix-2 decimation-in-frequency stage across lanes h and h ^ B of a quad:
-// the lower lane keeps self + partner, the upper one partner - self (sgn = -1).
-template <int B, int N>
-__device__ __forceinline__ void lane_dif_stage(float2 *w, float sgn) {
-    constexpr int kCtrl = B == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const float px = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w[m].x), kCtrl, 0xf, 0xf, false));
-        const float py = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w[m].y), kCtrl, 0xf, 0xf, false));
-        w[m] = make_float2(fmaf(sgn, w[m].x, px), fmaf(sgn, w[m].y, py));
-    }
 }
 
 constexpr int kThreads = 256;   // default workgroup size (see FCfg::THREADS)
@@ -133,21 +122,24 @@ struct FCfg {
     static constexpr int RED_BYTES = THREADS * (L1 + 1) * 4;
     // load the next item's frames while transforming the current one (where the
     // extra registers keep the occupancy)
-    static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && L <= 256;
+    static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && (L <= 256 || XP == MWAX_X_INT8);
     static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
 };
 
-// One complex int8 sample, converted exactly (one sign-extending byte convert
-// per component).
+// One complex int8 sample, converted exactly.  Written with arithmetic shifts of
+// the halfword placed in the upper half of a word so that each component is one
+// sign-extending byte-select convert (the int8_t casts of a 16-bit load compile
+// to a separate extract per component).
 __device__ __forceinline__ float2 load_pair(const uint8_t *p) {
-    const uint32_t w = *reinterpret_cast<const uint16_t *>(p);
-    return make_float2((float)(int8_t)w, (float)(int8_t)(w >> 8));
+    const int32_t w = (int32_t)((uint32_t)*reinterpret_cast<const uint16_t *>(p) << 16);
+    return make_float2((float)((w << 8) >> 24), (float)(w >> 24));
 }
 
 // The work of workgroup wg of nwg workgroups on the segment described by a;
 // DELAY: apply the fractional delay and phase correction before requantising.
 template <int L, int XP, bool STATS, bool DELAY = false>
-__device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const int nwg, uint8_t *smem) {
+__device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const int nwg, const int xoff,
+                                             uint8_t *smem) {
     using C = FCfg<L, XP>;
     constexpr int L1 = C::L1, L2 = C::L2, U = C::U, G = C::G, ES = C::ES, FPG = C::FPG;
     constexpr int GPW = C::GPW, PACKS = C::PACKS, R = C::R, CP = C::CP, SP = C::SP, EXG = C::EXG;
@@ -170,7 +162,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     float2 twr[kTwReg && L2 > 1 ? L1 : 1];
     if constexpr (kTwReg && L2 > 1) {
 #pragma unroll
-        for (int i = 0; i < L1; ++i) twr[i] = a.tw[(r * i) % L];        // W_L^(r k1)
+        for (int i = 1; i < L1; ++i) twr[i] = a.tw[(r * i) % L];        // W_L^(r k1)
     }
     float2 tw2[P > 1 ? L1 : 1];                                         // W_L2^(h m2), h = r % P
     if constexpr (P > 1) {
@@ -201,25 +193,38 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             const int nr = min(R, a.n_in - m0);
             const int64_t l0 = (int64_t)gs * G;
             const int fv = (int)min((int64_t)G, a.nframes - l0);
-            const int64_t sf = a.frame0 + l0;
+            // the item's first sample (uniform); a unit adds its row and offset
+            const int8_t *ib = a.volts + ((int64_t)m0 * a.ld + (a.frame0 + l0) * L) * 2;
 #pragma unroll
             for (int j = 0; j < NU; ++j) {
                 const int u = tid + j * C::THREADS;
                 const int sl = u / (G * UPF);
                 const int rem = u - sl * G * UPF;
-                const int f = rem / UPF, o = rem - f * UPF;
+                const int f = rem / UPF;
                 pre[j] = make_uint4(0u, 0u, 0u, 0u);     // frames past the end are zero
                 if (u < NUNITS && sl < nr && f < fv)
-                    pre[j] = *reinterpret_cast<const uint4 *>(
-                        a.volts + ((int64_t)(m0 + sl) * a.ld + (sf + f) * L) * 2 + o * 16);
+                    pre[j] = *reinterpret_cast<const uint4 *>(ib + (int64_t)sl * (2 * a.ld) + rem * 16);
             }
         }
     };
+    // Item of round t.  Workgroup b of a launch runs on XCD b mod 8, and each
+    // XCD has its own L2.  The output rows of consecutive items (adjacent inputs
+    // of one row group) share cache lines, so a round hands each XCD one
+    // contiguous range of items: a line is then completed in one L2 instead of
+    // leaving several L2s as partial 32- or 64-byte writes.  xoff: the XCD of
+    // workgroup 0 of this work (batched launches).
+    const bool xmap = (nwg & 7) == 0;
+    auto item_at = [&](int t) {
+        return t * nwg + (xmap ? ((wg + xoff) & 7) * (nwg >> 3) + (wg >> 3) : wg);
+    };
+    const int rounds = (items + nwg - 1) / nwg;
     if constexpr (C::PREFETCH) {
-        if (wg < items) fetch(wg);
+        if (item_at(0) < items) fetch(item_at(0));
     }
 
-    for (int item = wg; item < items; item += nwg) {
+    for (int round = 0; round < rounds; ++round) {
+        const int item = item_at(round);
+        if (item >= items) continue;   // the last round's tail (uniform per workgroup)
         const int gsel = item / nblk;
         const int n0 = (item - gsel * nblk) * R;
         const int nrows = min(R, a.n_in - n0);
@@ -239,7 +244,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
             }
             __syncthreads();
             if constexpr (C::PREFETCH) {
-                if (item + nwg < items) fetch(item + nwg);
+                if (round + 1 < rounds && item_at(round + 1) < items) fetch(item_at(round + 1));
             }
         }
         const int64_t lf0 = (int64_t)gsel * G;
@@ -308,8 +313,10 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                 dl_alpha = d * (1.0f / (float)L);
             }
 
-            // consume output slot i (FFT bin of this lane) with value X
-            auto emit = [&](int i, float2 X) {
+            // consume output slot i (FFT bin of this lane) with value X; tc: the
+            // frame's place in its pack as a compile-time constant (see emit_frame)
+            auto emit = [&](int i, float2 X, auto tc) {
+                constexpr int T = decltype(tc)::value;
                 if constexpr (DELAY) {
                     const int k = bin_of<L, XP>(r, i);
                     const float2 g = delay_gain(k < L / 2 ? k : k - L, dl_alpha, dl_phi);
@@ -335,7 +342,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                             // frame 1: pair it with the new code, one 16-bit write per half
                             constexpr int kW = (L1 + 3) / 4;
                             const int w = i / 4, p = i % 4;
-                            if (t == 0) {
+                            if constexpr (T == 0) {
                                 const uint32_t ins = (0x03020100u & ~(0xffu << (8 * p))) | (0x04u << (8 * p));
                                 q0[w] = __builtin_amdgcn_perm(br, q0[w], ins);
                                 q0[kW + w] = __builtin_amdgcn_perm(bi, q0[kW + w], ins);
@@ -350,7 +357,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                         const uint32_t br = (uint32_t)__builtin_bit_cast(uint16_t, hr);
                         const uint32_t bi = (uint32_t)__builtin_bit_cast(uint16_t, hi);
                         if constexpr (FPG == 2) {
-                            if (t == 0) {
+                            if constexpr (T == 0) {
                                 q0[2 * i] = br;
                                 q0[2 * i + 1] = bi;
                             } else {
@@ -358,8 +365,8 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                                 *reinterpret_cast<uint32_t *>(row + IM) = q0[2 * i + 1] | (bi << 16);
                             }
                         } else {
-                            *reinterpret_cast<uint16_t *>(row + 2 * t) = (uint16_t)br;
-                            *reinterpret_cast<uint16_t *>(row + IM + 2 * t) = (uint16_t)bi;
+                            *reinterpret_cast<uint16_t *>(row) = (uint16_t)br;
+                            *reinterpret_cast<uint16_t *>(row + IM) = (uint16_t)bi;
                         }
                     } else {
                         *reinterpret_cast<float *>(row) = X.x;
@@ -367,13 +374,21 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     }
                 }
             };
+            // run body(tc) with the frame's place in the pack as a constant, so that
+            // the emission of a two-frame pack has no per-slot branch on t
+            auto emit_frame = [&](auto body) {
+                if (FPG == 1 || t == 0) body(std::integral_constant<int, 0>{});
+                else body(std::integral_constant<int, 1>{});
+            };
 
             if constexpr (L2 == 1) {
+                emit_frame([&](auto tc) {
 #pragma unroll
-                for (int k = 0; k < L1; ++k) emit(k, v[k]);
+                    for (int k = 0; k < L1; ++k) emit(k, v[k], tc);
+                });
             } else {
 #pragma unroll
-                for (int k1 = 0; k1 < L1; ++k1) {
+                for (int k1 = 1; k1 < L1; ++k1) {      // W_L^0 = 1
                     float2 w;
                     if constexpr (kTwReg) w = twr[k1];
                     else w = a.tw[(r * k1) % L];
@@ -383,10 +398,11 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     // lane r writes its column of the L1 x L2 block (row pitch
                     // L2 + P keeps the writes and the strided reads below free of
                     // bank conflicts); lane (k1, h) = (r / P, r % P) then takes
-                    // rows h + P m of column k1: an in-lane 16-point DFT, the
-                    // twiddle W_L2^(h m2), and log2 P radix-2 stages across the P
-                    // lanes, after which lane h holds block q = bitrev_P(h) of
-                    // that column's transform
+                    // rows h + P m of column k1, an in-lane 16-point DFT over m, and
+                    // the twiddle W_L2^(h m2).  A second exchange hands lane
+                    // (k1, g) the P values over h of the columns m2 = g + P j, whose
+                    // P-point DFTs complete the column's transform: slot j P + q of
+                    // the lane holds bin k1 + L1 (g + P j + L1 q)
                     float2 *eg = ex + gg * EXG;
 #pragma unroll
                     for (int k1 = 0; k1 < L1; ++k1) eg[k1 * C::EXR + r] = v[k1];
@@ -400,16 +416,24 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     for (int m = 1; m < L1; ++m)
                         w[m] = make_float2(w[m].x * tw2[m].x - w[m].y * tw2[m].y,
                                            w[m].x * tw2[m].y + w[m].y * tw2[m].x);
-                    if constexpr (P == 4) {
-                        lane_dif_stage<2, L1>(w, (h & 2) ? -1.0f : 1.0f);
-                        if (h == 3) {       // upper half, second lane: times W_4 = -i
+                    // lane rows of L1 + 1 float2: writes (fixed m) and reads (fixed
+                    // h, j) both fall in distinct banks
+                    constexpr int XR = L1 + 1;
+                    static_assert(C::L2 * XR <= EXG, "second exchange exceeds the group's area");
+                    wave_sync();   // the first exchange has been read
 #pragma unroll
-                            for (int m = 0; m < L1; ++m) w[m] = make_float2(w[m].y, -w[m].x);
-                        }
+                    for (int m = 0; m < L1; ++m) eg[r * XR + m] = w[m];
+                    wave_sync();
+#pragma unroll
+                    for (int j = 0; j < L1 / P; ++j) {
+#pragma unroll
+                        for (int q = 0; q < P; ++q) w[j * P + q] = eg[(k1 * P + q) * XR + h + P * j];
+                        dft_regs<P>(w + j * P);
                     }
-                    lane_dif_stage<1, L1>(w, (h & 1) ? -1.0f : 1.0f);
+                    emit_frame([&](auto tc) {
 #pragma unroll
-                    for (int m2 = 0; m2 < L1; ++m2) emit(m2, w[m2]);
+                        for (int i = 0; i < L1; ++i) emit(i, w[i], tc);
+                    });
                 } else {
                     // exchange through LDS; column swizzle r ^ (k1 / U) keeps both the
                     // writes (fixed k1) and the reads (fixed r2) free of bank conflicts
@@ -424,8 +448,10 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 #pragma unroll
                         for (int r2 = 0; r2 < L2; ++r2) w[r2] = eg[k1 * L2 + (r2 ^ r)];
                         dft_regs<L2>(w);
+                        emit_frame([&](auto tc) {
 #pragma unroll
-                        for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2]);
+                            for (int k2 = 0; k2 < L2; ++k2) emit(u * L2 + k2, w[k2], tc);
+                        });
                     }
                 }
                 wave_sync();
@@ -434,16 +460,26 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 
         if constexpr (!STATS) {
             __syncthreads();
-            // store the image: per channel, nrows rows of 32 bytes, 16 bytes per thread
-            const int units = L * nrows * 2;
-            for (int u = tid; u < units; u += C::THREADS) {
-                const int c = u / (nrows * 2);
-                const int rem = u - c * nrows * 2;
-                const int sl = rem >> 1, h = rem & 1;
-                const uint32_t *src = reinterpret_cast<const uint32_t *>(outbuf + c * CP + sl * kRowBytes + h * 16);
-                const uint4 val = make_uint4(src[0], src[1], src[2], src[3]);
-                uint8_t *dst = a.chan + ((((int64_t)c * a.NG + a.grp0 + gsel) * a.n_in) + n0 + sl) * kRowBytes + h * 16;
-                *reinterpret_cast<uint4 *>(dst) = val;
+            // store the image: per channel, nrows rows of 32 bytes, 16 bytes per
+            // thread; unit u = (c, 16-byte piece e of the channel's nrows rows)
+            const int64_t cstride = a.NG * a.n_in * kRowBytes;    // bytes per channel
+            uint8_t *db = a.chan + ((a.grp0 + gsel) * a.n_in + n0) * kRowBytes;
+            auto store_unit = [&](int c, int e) {
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(outbuf + c * CP + e * 16);
+                *reinterpret_cast<uint4 *>(db + c * cstride + e * 16) = make_uint4(src[0], src[1], src[2], src[3]);
+            };
+            constexpr int SU = L * R * 2, NJ = (SU + C::THREADS - 1) / C::THREADS;
+            if (nrows == R && NJ <= 2) {
+                // unrolled (more units per thread would hold their loads in registers)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const int u = tid + j * C::THREADS;
+                    if (SU % C::THREADS == 0 || u < SU) store_unit(u / (2 * R), u % (2 * R));
+                }
+            } else if (nrows == R) {
+                for (int u = tid; u < SU; u += C::THREADS) store_unit(u / (2 * R), u % (2 * R));
+            } else {
+                for (int u = tid; u < L * nrows * 2; u += C::THREADS) store_unit(u / (nrows * 2), u % (nrows * 2));
             }
         }
     }
@@ -478,7 +514,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 template <int L, int XP, bool STATS, bool DELAY>
 __global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_kernel(FArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    fengine_body<L, XP, STATS, DELAY>(a, blockIdx.x, gridDim.x, smem);
+    fengine_body<L, XP, STATS, DELAY>(a, blockIdx.x, gridDim.x, 0, smem);
 }
 
 // Batched form: workgroups [block0[d], block0[d+1]) of the launch work on
@@ -494,7 +530,7 @@ __global__ __launch_bounds__((FCfg<L, XP>::THREADS)) void fengine_batch_kernel(F
     while (load_uniform(b.block0 + d + 1) <= blk) ++d;
     const FArgs a = load_uniform(b.desc + d);
     const int first = load_uniform(b.block0 + d), count = load_uniform(b.block0 + d + 1) - first;
-    fengine_body<L, XP, STATS>(a, blk - first, count, smem);
+    fengine_body<L, XP, STATS>(a, blk - first, count, first & 7, smem);
 }
 
 template <int L, int XP>
