@@ -26,15 +26,15 @@ namespace {
 using namespace fft;
 
 // Two-pass split L = L1 * L2 over an FFT group of L2 lanes.  Pass 2 (length L2)
-// is done by each lane on U columns when L2 <= L1.  INT8 at L >= 512 keeps 16
-// points per lane (L2 = 32 or 64 > L1 = 16): each pass-2 transform is shared by
+// is done by each lane on U columns when L2 <= L1.  At L >= 512 a lane keeps 16
+// points (L2 = 32 or 64 > L1 = 16): each pass-2 transform is shared by
 // P = L2 / 16 neighbouring lanes, an in-lane 16-point DFT, a second exchange and
-// in-lane P-point DFTs (see fengine_body).  Measured: 1.2x (L = 1024) and 1.1x
-// (L = 512) over 32 points per lane for INT8, 0.9x for binary16, whose 32-point
-// kernels do not spill.
+// in-lane P-point DFTs (see fengine_body).  Measured against 32 points per lane:
+// 1.2x (L = 1024) and 1.1x (L = 512) for INT8, 1.12x / 1.13x for binary16,
+// 1.06x / 1.12x for FP32 (about 150 instead of 230-280 VGPRs).
 template <int L, int XP>
 struct FftShape {
-    static constexpr bool kLaneSplit = XP == MWAX_X_INT8 && L >= 512;
+    static constexpr bool kLaneSplit = L >= 512;
     static constexpr int L2 = L <= 16 ? 1
                               : (L == 32 ? 4
                               : (L <= 128 ? 8 : (L == 256 ? 16 : (kLaneSplit ? L / 16 : (L == 512 ? 16 : 32)))));
@@ -101,10 +101,11 @@ struct FCfg {
     // registers than packing two frames' codes, for more waves per SIMD.  At
     // L >= 512 (32 or 64 lanes per FFT) an INT8 group transforms two frames,
     // so that a workgroup still covers the 16 frames of a row group, and
-    // L = 1024 (one FFT per wave) takes eight waves.  Binary16 keeps one frame
-    // per group (two would need 86 KB of LDS at L = 128, one workgroup per CU).
+    // L = 1024 (one FFT per wave) takes eight waves at every precision (two
+    // inputs per item for FP32: 64-byte runs per channel).  Binary16 keeps one
+    // frame per group (two would need 86 KB of LDS at L = 128, one workgroup per CU).
     static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 && L <= 256 ? 1 : 2) : 1;
-    static constexpr int THREADS = L == 1024 && XP == MWAX_X_INT8 ? 512 : kThreads;
+    static constexpr int THREADS = L == 1024 ? 512 : kThreads;
     static constexpr int P = SH::P;
     static constexpr int GPW = 64 / L2;
     static constexpr int NGWG = THREADS / 64 * GPW;   // FFT groups per workgroup
