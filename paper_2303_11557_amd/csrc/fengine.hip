@@ -7,7 +7,8 @@
 //
 // One workgroup owns R inputs x G consecutive frames of one integration
 // segment = one 32-byte row group per (channel, input).  The raw int8 frames
-// are staged in LDS with coalesced 16-byte loads; each FFT is computed by a
+// are staged in LDS with coalesced 16-byte loads (INT8 at L = 1024: loaded by
+// the FFT lanes themselves, see FCfg::DIRECT); each FFT is computed by a
 // group of L2 lanes holding L1 = L / L2 points each:
 //   X[k1 + L1 k2] = sum_r W_L2^(r k2) W_L^(r k1) sum_n1 x[r + L2 n1] W_L1^(n1 k1)
 // (a two-pass Cooley-Tukey split): pass 1 in registers per lane, twiddle,
@@ -105,26 +106,35 @@ struct FCfg {
     // inputs per item for FP32: 64-byte runs per channel).  Binary16 keeps one
     // frame per group (two would need 86 KB of LDS at L = 128, one workgroup per CU).
     static constexpr int FPG = XP == MWAX_X_INT8 ? (L >= 16 && L <= 256 ? 1 : 2) : 1;
-    static constexpr int THREADS = L == 1024 ? 512 : kThreads;
+    // INT8 at L = 1024: four waves, each transforming two packs of an item in
+    // turn, its lanes loading their own samples straight from HBM (a lane's
+    // samples r + 64 n1 of a frame are one 128-byte line per load instruction).
+    // Without the staging area a workgroup needs 71 KB of LDS, so two fit a CU
+    // and one workgroup's barriers and image store overlap the other's FFTs:
+    // 2.34 instead of 1.86 TB/s.  (At L = 512, two 32-lane groups per wave,
+    // the same scheme ran at 2.04 instead of 2.37 TB/s.)
+    static constexpr bool DIRECT = XP == MWAX_X_INT8 && L == 1024;
+    static constexpr int THREADS = DIRECT ? kThreads : (L == 1024 ? 512 : kThreads);
     static constexpr int P = SH::P;
     static constexpr int GPW = 64 / L2;
     static constexpr int NGWG = THREADS / 64 * GPW;   // FFT groups per workgroup
     static constexpr int PACKS = G / FPG;         // frame packs per input
-    static constexpr int R = NGWG / PACKS;        // inputs per workgroup item
+    static constexpr int R = NGWG >= PACKS ? NGWG / PACKS : 1;   // inputs per workgroup item
+    static constexpr int PPG = PACKS * R / NGWG;  // packs per group and item
     static constexpr int CP = R * kRowBytes + cp_pad(L, XP);
     static constexpr int SP = 2 * L + 16;         // staged frame pitch (bytes)
     // exchange area per group (float2): L + 8, or L1 rows of L2 + P (P > 1)
     static constexpr int EXR = L2 + P;
     static constexpr int EXG = P > 1 ? L1 * EXR : L + 8;
     static constexpr int OUT_BYTES = L * CP;
-    static constexpr int STAGE_BYTES = L2 > 1 ? R * G * SP : 0;
+    static constexpr int STAGE_BYTES = L2 > 1 && !DIRECT ? R * G * SP : 0;
     static constexpr int EX_BYTES = L2 > 1 ? NGWG * EXG * 8 : 0;
     // statistics pass: per-lane channel sums (L1 floats) and populated-frame counts
     static constexpr int RED_BYTES = THREADS * (L1 + 1) * 4;
     // load the next item's frames while transforming the current one (where the
     // extra registers keep the occupancy)
-    static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && (L <= 256 || XP == MWAX_X_INT8);
-    static_assert(R >= 1 && NGWG % PACKS == 0, "bad decomposition");
+    static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && (L <= 256 || XP == MWAX_X_INT8) && !DIRECT;
+    static_assert(R >= 1 && NGWG * PPG == PACKS * R && (PPG == 1 || GPW == 1), "bad decomposition");
 };
 
 // One complex int8 sample, converted exactly.  Written with arithmetic shifts of
@@ -151,8 +161,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = lane / L2, r = lane % L2;
     const int gg = wave * GPW + gi;            // FFT group within the workgroup
-    const int nl = gg / PACKS;                 // its input within the item
-    const int pk = gg - nl * PACKS;            // its frame pack: frames pk*FPG + t
+    constexpr int PPG = C::PPG;                // packs gg PPG + pp of the item are group gg's
     const int nblk = (a.n_in + R - 1) / R;
     const int items = a.ngrp * nblk;
 
@@ -184,7 +193,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     // PREFETCH the global loads of the next item are issued before the current
     // item is transformed, so their latency hides behind the FFT work.
     constexpr int UPF = 2 * L / 16;                      // 16-byte units per frame
-    constexpr int NUNITS = L2 > 1 ? R * G * UPF : 0;
+    constexpr int NUNITS = L2 > 1 && !C::DIRECT ? R * G * UPF : 0;
     constexpr int NU = (NUNITS + C::THREADS - 1) / C::THREADS;
     uint4 pre[NU > 0 ? NU : 1];
     auto fetch = [&](int it) {
@@ -222,6 +231,31 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
     if constexpr (C::PREFETCH) {
         if (item_at(0) < items) fetch(item_at(0));
     }
+    // DIRECT: the 16-bit samples of the group's next frame (q = pp FPG + t of
+    // item it), loaded while the current frame is transformed; zeros past the
+    // segment or the inputs
+    uint32_t raw[C::DIRECT ? L1 : 1];
+    auto fetch_frame = [&](int it, int q) {
+        if constexpr (C::DIRECT) {
+            const int gs = it / nblk;
+            const int pg = gg * PPG + q / FPG;
+            const int ni = (it - gs * nblk) * R + pg / PACKS;
+            const int f = (pg % PACKS) * FPG + q % FPG;
+            const int64_t l0 = (int64_t)gs * G;
+            if (ni < a.n_in && f < (int)min((int64_t)G, a.nframes - l0)) {
+                const uint16_t *src = reinterpret_cast<const uint16_t *>(
+                                          a.volts + ((int64_t)ni * a.ld + (a.frame0 + l0 + f) * L) * 2) + r;
+#pragma unroll
+                for (int n1 = 0; n1 < L1; ++n1) raw[n1] = src[L2 * n1];
+            } else {
+#pragma unroll
+                for (int n1 = 0; n1 < L1; ++n1) raw[n1] = 0u;
+            }
+        }
+    };
+    if constexpr (C::DIRECT) {
+        if (item_at(0) < items) fetch_frame(item_at(0), 0);
+    }
 
     for (int round = 0; round < rounds; ++round) {
         const int item = item_at(round);
@@ -231,7 +265,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         const int nrows = min(R, a.n_in - n0);
 
         __syncthreads();  // LDS of the previous item fully consumed
-        if constexpr (L2 > 1) {
+        if constexpr (L2 > 1 && !C::DIRECT) {
             if constexpr (!C::PREFETCH) fetch(item);
 #pragma unroll
             for (int j = 0; j < NU; ++j) {
@@ -252,6 +286,9 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         const int fvalid = (int)min((int64_t)G, a.nframes - lf0);
         const int64_t src_frame = a.frame0 + lf0;
 
+        for (int pp = 0; pp < PPG; ++pp) {
+        const int nl = (gg * PPG + pp) / PACKS;           // the pack's input within the item
+        const int pk = (gg * PPG + pp) - nl * PACKS;      // and its frames pk FPG + t
         // first frame of the pack: binary16 bits per slot, or int8 codes packed four
         // to a word (re words, then im words)
         constexpr int kQ0 = XP == MWAX_X_INT8 ? 2 * ((L1 + 3) / 4) : 2 * L1;
@@ -263,7 +300,17 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
         for (int t = 0; t < FPG; ++t) {
             const int f = pk * FPG + t;
             float2 v[L1];
-            if constexpr (L2 == 1) {
+            if constexpr (C::DIRECT) {
+#pragma unroll
+                for (int n1 = 0; n1 < L1; ++n1) {
+                    const int32_t w = (int32_t)(raw[n1] << 16);
+                    v[n1] = make_float2((float)((w << 8) >> 24), (float)(w >> 24));
+                }
+                // start the loads of the group's next frame (in this item or the next)
+                const int q = pp * FPG + t + 1;
+                if (q < PPG * FPG) fetch_frame(item, q);
+                else if (round + 1 < rounds && item_at(round + 1) < items) fetch_frame(item_at(round + 1), 0);
+            } else if constexpr (L2 == 1) {
                 if (nl < nrows && f < fvalid) {
                     const uint8_t *src = reinterpret_cast<const uint8_t *>(a.volts) +
                                          ((int64_t)(n0 + nl) * a.ld + (src_frame + f) * L) * 2;
@@ -458,6 +505,7 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                 wave_sync();
             }
         }
+        }   // packs of the group
 
         if constexpr (!STATS) {
             __syncthreads();
