@@ -174,10 +174,16 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 #pragma unroll
         for (int i = 1; i < L1; ++i) twr[i] = a.tw[(r * i) % L];        // W_L^(r k1)
     }
-    float2 tw2[P > 1 ? L1 : 1];                                         // W_L2^(h m2), h = r % P
+    // W_L2^(q m2) for the values q = 1 .. P-1 of the columns m2 = g + P j that
+    // lane (k1, g) = (r / P, r % P) transforms after the second exchange
+    constexpr int kTw2 = P > 1 ? (P - 1) * (L1 / P) : 1;
+    float2 tw2[kTw2];
     if constexpr (P > 1) {
 #pragma unroll
-        for (int m = 0; m < L1; ++m) tw2[m] = a.tw[(((r % P) * m) % L2) * (L / L2)];
+        for (int q = 1; q < P; ++q)
+#pragma unroll
+            for (int j = 0; j < L1 / P; ++j)
+                tw2[(q - 1) * (L1 / P) + j] = a.tw[((q * (r % P + P * j)) % L2) * (L / L2)];
     }
     float sc[XP == MWAX_X_INT8 && kTwReg && !STATS ? L1 : 1];
     if constexpr (XP == MWAX_X_INT8 && kTwReg && !STATS) {
@@ -446,11 +452,11 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
                     // lane r writes its column of the L1 x L2 block (row pitch
                     // L2 + P keeps the writes and the strided reads below free of
                     // bank conflicts); lane (k1, h) = (r / P, r % P) then takes
-                    // rows h + P m of column k1, an in-lane 16-point DFT over m, and
-                    // the twiddle W_L2^(h m2).  A second exchange hands lane
-                    // (k1, g) the P values over h of the columns m2 = g + P j, whose
-                    // P-point DFTs complete the column's transform: slot j P + q of
-                    // the lane holds bin k1 + L1 (g + P j + L1 q)
+                    // rows h + P m of column k1 and an in-lane 16-point DFT over m.
+                    // A second exchange hands lane (k1, g) the P values over h of the
+                    // columns m2 = g + P j; each takes the twiddle W_L2^(h m2) (none
+                    // for h = 0) and their P-point DFTs complete the column's
+                    // transform: slot j P + q of the lane holds bin k1 + L1 (g + P j + L1 q)
                     float2 *eg = ex + gg * EXG;
 #pragma unroll
                     for (int k1 = 0; k1 < L1; ++k1) eg[k1 * C::EXR + r] = v[k1];
@@ -460,10 +466,6 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 #pragma unroll
                     for (int m = 0; m < L1; ++m) w[m] = eg[k1 * C::EXR + h + P * m];
                     dft_regs<L1>(w);
-#pragma unroll
-                    for (int m = 1; m < L1; ++m)
-                        w[m] = make_float2(w[m].x * tw2[m].x - w[m].y * tw2[m].y,
-                                           w[m].x * tw2[m].y + w[m].y * tw2[m].x);
                     // lane rows of L1 + 1 float2: writes (fixed m) and reads (fixed
                     // h, j) both fall in distinct banks
                     constexpr int XR = L1 + 1;
@@ -475,7 +477,14 @@ __device__ __forceinline__ void fengine_body(const FArgs &a, const int wg, const
 #pragma unroll
                     for (int j = 0; j < L1 / P; ++j) {
 #pragma unroll
-                        for (int q = 0; q < P; ++q) w[j * P + q] = eg[(k1 * P + q) * XR + h + P * j];
+                        for (int q = 0; q < P; ++q) {
+                            float2 y = eg[(k1 * P + q) * XR + h + P * j];
+                            if (q > 0) {
+                                const float2 t = tw2[(q - 1) * (L1 / P) + j];
+                                y = make_float2(y.x * t.x - y.y * t.y, y.x * t.y + y.y * t.x);
+                            }
+                            w[j * P + q] = y;
+                        }
                         dft_regs<P>(w + j * P);
                     }
                     emit_frame([&](auto tc) {
