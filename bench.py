@@ -220,6 +220,7 @@ def main_batch(args):
         t0 = time.perf_counter()
         kc, grid = b.autotune([v[:, :chunk] for v in volts], trials=3)
         tune_s = time.perf_counter() - t0
+        tiles = b.tiles()
 
         def step():
             for k in range(ncalls):
@@ -245,6 +246,15 @@ def main_batch(args):
         step()
         fam = {name: b.kernel_time(i) for i, name in
                ((0, "fengine"), (1, "xengine"), (3, "calib"), (4, "call"))}
+        # the same eager pass with every instance on each tile edge, for the
+        # record of what the tuner's tile choice is worth
+        x_by_tile = {}
+        for te in (128, 64):
+            b.set_tiles([te] * len(cfgs))
+            b.kernel_time(1)
+            step()
+            x_by_tile[te] = round(b.kernel_time(1)[0] / ncalls, 3)
+        b.set_tiles(tiles)
         b.set_timing(False)
         b.set_graph(True)
         eager_ms = fam["call"][0]
@@ -282,7 +292,9 @@ def main_batch(args):
         "graph_replay": True,
         "eager_ms_per_step": round(eager_ms, 3),
         "calibration_ms_per_step": round(fam["calib"][0], 3),
-        "autotune": {"kchunk": kc, "grid": grid, "seconds": round(tune_s, 2)},
+        "autotune": {"kchunk": kc, "tile": tiles, "grid": grid, "seconds": round(tune_s, 2),
+                     "xengine_ms_per_call": {"tuned": round(x_ms / max(ncalls, 1), 3),
+                                             "all_tile_128": x_by_tile[128], "all_tile_64": x_by_tile[64]}},
         "roofline": dominant, "roofline_other": other,
         "cpu_baseline": cpu,
     }

@@ -358,12 +358,19 @@ mwax_status mwax_batch_run(mwax_batch b, const int8_t *const *d_volts, const int
 
 /* Autotuner: on the given block (as for mwax_batch_run, every n_samples[i] >
  * 0), channelise once, then time the persistent X-engine on the device for
- * candidate work shapes: per instance shape (inputs, L), the number of row
- * groups per work item (whole segments, or chunks of 4096 .. 128 row groups;
- * INT8 only, chunks of one tile then flush with exact int64 atomic adds), and
- * the persistent grid size.  Each candidate is timed `trials` times (median);
- * the fastest is kept.  Needs every instance at stream position 0 with nothing
- * accumulated (MWAX_E_STATE otherwise) and resets every instance afterwards. */
+ * candidate work shapes: per instance shape (inputs, L), the MFMA tile edge
+ * (128 x 128 tiles, four waves of 64 x 64; or 64 x 64 tiles, four waves of
+ * 32 x 32, which waste less of the diagonal tiles on small instances) and the
+ * number of row groups per work item (whole segments, or chunks of 4096 .. 128
+ * row groups; INT8 only, chunks of one tile then flush with exact int64 atomic
+ * adds), and the persistent grid size.  Each candidate is timed `trials` times
+ * (median); the fastest is kept.  With a tuning cache set
+ * (mwax_batch_set_tuning_cache), shape classes found in it take their cached
+ * choice untimed (and, when every class and the batch's grid are cached, no
+ * trial runs at all); the choices made are written back to it, keyed by
+ * (architecture, inputs, L, precision).  Needs every instance at stream
+ * position 0 with nothing accumulated (MWAX_E_STATE otherwise) and resets
+ * every instance afterwards, except when everything came from the cache. */
 mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, const int64_t *n_samples,
                                 const int64_t *ld_samples, int32_t trials);
 
@@ -372,6 +379,21 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
  * 0, or >= 1 for INT8 batches; grid 0 = the device's resident maximum). */
 mwax_status mwax_batch_get_tuning(mwax_batch b, int32_t *kchunk, int32_t *grid);
 mwax_status mwax_batch_set_tuning(mwax_batch b, const int32_t *kchunk, int32_t grid);
+
+/* The X-engine tile edge per instance (host arrays of n entries): 128 (the
+ * default, as single plans) or 64.  set_tiles refuses other values and a 64
+ * edge where an instance would need more than 256 tiles per channel
+ * (MWAX_E_INVAL), and pending blocks (MWAX_E_STATE).  Any tiling computes the
+ * same sums (INT8: bit-identical); only the work split changes. */
+mwax_status mwax_batch_get_tiles(mwax_batch b, int32_t *tile);
+mwax_status mwax_batch_set_tiles(mwax_batch b, const int32_t *tile);
+
+/* The autotuner's on-disk cache: a text file (path, NUL-terminated host string,
+ * copied) read before and rewritten after each mwax_batch_autotune; NULL or ""
+ * turns it off (the default).  Entries: "shape <arch> <inputs> <L> <xprec>
+ * <tile> <kchunk>" and "grid <arch> <classes> <xprec> <grid>".  A file that
+ * cannot be written makes the autotuner return MWAX_E_INVAL after tuning. */
+mwax_status mwax_batch_set_tuning_cache(mwax_batch b, const char *path);
 
 /* Graph replay on (1, the default) or off (0: the same launches issued one by
  * one, which also allows per-kernel timing). */

@@ -15,8 +15,12 @@
 // fixed launch sequence runs, captured once as a HIP graph and replayed.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <numeric>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "plan.h"
@@ -59,7 +63,9 @@ struct mwax_batch_s {
 
     // tuning
     std::vector<int> kchunk;        // row groups per X item, 0 = whole segment
+    std::vector<int> tile;          // X-engine tile edge per instance (128 or 64)
     int xgrid = 0, xgrid_max = 0;
+    std::string cache_path;         // autotuner's on-disk cache ("" = none)
 
     // tables
     size_t bytes = 0, off_upload = 0;
@@ -160,6 +166,13 @@ int64_t eff_chunk(mwax_batch b, int i) {
 
 int nblk_of(mwax_plan p) { return (p->n_in + p->R - 1) / p->R; }
 
+// X-engine tiles per channel of instance i at its tile edge.
+int ntiles_of(mwax_batch b, int i) { return xengine_tile_count(b->inst[i]->n_in, b->tile[i]); }
+// Tile edges instance i may take: a work item names its tile in 8 bits.
+bool tile_allowed(mwax_batch b, int i, int te) {
+    return (te == kXTile || te == kXTileSmall) && xengine_tile_count(b->inst[i]->n_in, te) <= kXBatchMaxTiles;
+}
+
 // Whole-segment work items overwrite a slot with the first flush of each
 // integration, so emitting an integration need not clear its slot; chunked INT8
 // items add atomically and need cleared slots.  Slots emitted without clearing
@@ -223,7 +236,7 @@ mwax_status layout(mwax_batch b) {
         b->max_xdesc += b->max_segs[i];
         const int64_t kc = eff_chunk(b, i);
         const int64_t chunks = kc ? ceil_div(p->NG, kc) + b->max_segs[i] : b->max_segs[i];
-        b->max_items += (int64_t)p->L * p->ntiles * chunks;
+        b->max_items += (int64_t)p->L * ntiles_of(b, i) * chunks;
     }
     if (b->max_xdesc > kXBatchMaxDesc)
         return fail(MWAX_E_UNSUPPORTED, "batch needs %d segment descriptors per call, at most %d are supported",
@@ -348,13 +361,15 @@ void build_x_tables(mwax_batch b, const std::vector<std::vector<Segment>> &segs,
             x.ksplit = (int32_t)ceil_div(s.ngrp, x.kchunk);
             x.first = xa.first;
             x.i32 = xa.i32;
+            x.te = b->tile[i];
+            const int nt = ntiles_of(b, i);
             const int d = (int)t.xd.size();
             t.xd.push_back(x);
             t.xd_inst.push_back(i);
             for (int c = 0; c < p->L; ++c)
                 for (int k = 0; k < x.ksplit; ++k) {
                     const int64_t g = std::min<int64_t>(x.kchunk, s.ngrp - (int64_t)k * x.kchunk);
-                    units.push_back({d, c, k, p->ntiles, (int64_t)p->ntiles * (g + kUnitOverheadGroups)});
+                    units.push_back({d, c, k, nt, (int64_t)nt * (g + kUnitOverheadGroups)});
                 }
         }
     }
@@ -562,6 +577,93 @@ mwax_status run_tables(mwax_batch b, const CallTables &t, bool x_only, bool allo
     return MWAX_OK;
 }
 
+// The autotuner's on-disk cache, a text file of one entry per line:
+//   shape <arch> <n_in> <L> <xprec> <tile> <kchunk>   the choice for a shape class
+//   grid <arch> <classes> <xprec> <grid>               the persistent grid of a batch
+// (<classes>: the batch's shape classes as n_in x L x count, comma-separated).
+// Lines that do not parse are dropped when the file is rewritten.
+struct TuneCache {
+    struct Entry {
+        std::string arch;
+        int n_in, L, xprec, tile, kchunk;
+    };
+    struct GridEntry {
+        std::string arch, sig;
+        int xprec, grid;
+    };
+    std::vector<Entry> shapes;
+    std::vector<GridEntry> grids;
+
+    void read(const std::string &path) {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            std::istringstream in(line);
+            std::string kind;
+            in >> kind;
+            if (kind == "shape") {
+                Entry e;
+                if (in >> e.arch >> e.n_in >> e.L >> e.xprec >> e.tile >> e.kchunk) put(e.arch, e.n_in, e.L, e.xprec, e.tile, e.kchunk);
+            } else if (kind == "grid") {
+                GridEntry g;
+                if (in >> g.arch >> g.sig >> g.xprec >> g.grid && g.grid > 0) put_grid(g.arch, g.sig, g.xprec, g.grid);
+            }
+        }
+    }
+    const Entry *find(const std::string &arch, int n_in, int L, int xprec) const {
+        for (const Entry &e : shapes)
+            if (e.arch == arch && e.n_in == n_in && e.L == L && e.xprec == xprec) return &e;
+        return nullptr;
+    }
+    int grid(const std::string &arch, const std::string &sig, int xprec) const {
+        for (const GridEntry &g : grids)
+            if (g.arch == arch && g.sig == sig && g.xprec == xprec) return g.grid;
+        return 0;
+    }
+    void put(const std::string &arch, int n_in, int L, int xprec, int tile, int kchunk) {
+        for (Entry &e : shapes)
+            if (e.arch == arch && e.n_in == n_in && e.L == L && e.xprec == xprec) {
+                e.tile = tile;
+                e.kchunk = kchunk;
+                return;
+            }
+        shapes.push_back({arch, n_in, L, xprec, tile, kchunk});
+    }
+    void put_grid(const std::string &arch, const std::string &sig, int xprec, int grid_) {
+        for (GridEntry &g : grids)
+            if (g.arch == arch && g.sig == sig && g.xprec == xprec) {
+                g.grid = grid_;
+                return;
+            }
+        grids.push_back({arch, sig, xprec, grid_});
+    }
+    // written to a temporary file, then renamed over the old one
+    bool write(const std::string &path) const {
+        const std::string tmp = path + ".tmp";
+        {
+            std::ofstream f(tmp, std::ios::trunc);
+            if (!f) return false;
+            for (const Entry &e : shapes)
+                f << "shape " << e.arch << ' ' << e.n_in << ' ' << e.L << ' ' << e.xprec << ' ' << e.tile << ' '
+                  << e.kchunk << '\n';
+            for (const GridEntry &g : grids)
+                f << "grid " << g.arch << ' ' << g.sig << ' ' << g.xprec << ' ' << g.grid << '\n';
+            if (!f) return false;
+        }
+        return std::rename(tmp.c_str(), path.c_str()) == 0;
+    }
+};
+
+// The device's architecture name without its feature suffixes (e.g. gfx950).
+std::string device_arch(int dev) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    const size_t c = a.find(':');
+    if (c != std::string::npos) a.resize(c);
+    return a.empty() ? "unknown" : a;
+}
+
 void collect_times(mwax_batch b) {
     for (auto &ev : b->events) {
         float ms = 0.0f;
@@ -646,6 +748,7 @@ mwax_status mwax_batch_create(const mwax_config *cfgs, int32_t n, void *hip_stre
         b->group_of.push_back(gi);
     }
     b->kchunk.assign(n, 0);
+    b->tile.assign(n, kXTile);
     b->xgrid_max = xengine_batch_max_grid(b->xprec, b->device);
     b->xgrid = b->xgrid_max;
     mwax_status st = layout(b);
@@ -703,15 +806,71 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
     mwax_status st = prepare_call(b, d_volts, n_samples, ld_samples, segs, active);
     if (st != MWAX_OK) return st;
 
-    // candidate chunk sizes need the tables sized for the smallest chunk
+    // candidates: tile edge x row groups per work item (chunks: INT8 only)
     const std::vector<int> chunks = b->xprec == MWAX_X_INT8 ? std::vector<int>{0, 4096, 2048, 1024, 512, 256, 128}
                                                             : std::vector<int>{0};
-    const std::vector<int> saved_kc = b->kchunk;
+    const std::vector<int> tiles = {kXTile, kXTileSmall};
+    const std::vector<int> saved_kc = b->kchunk, saved_tile = b->tile;
     const int saved_grid = b->xgrid;
+
+    // instance shape classes (inputs, L), heaviest first
+    std::vector<std::pair<int64_t, std::vector<int>>> classes;
+    for (int i = 0; i < b->n; ++i) {
+        mwax_plan p = b->inst[i];
+        bool placed = false;
+        for (auto &c : classes) {
+            mwax_plan q = b->inst[c.second[0]];
+            if (q->n_in == p->n_in && q->L == p->L) {
+                c.second.push_back(i);
+                c.first += p->P * n_samples[i];
+                placed = true;
+            }
+        }
+        if (!placed) classes.push_back({p->P * n_samples[i], {i}});
+    }
+    std::stable_sort(classes.begin(), classes.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+
+    // the on-disk cache: a shape class found there keeps its entry untimed
+    TuneCache cache;
+    const std::string arch = device_arch(b->device);
+    if (!b->cache_path.empty()) cache.read(b->cache_path);
+    std::vector<bool> cached(classes.size(), false);
+    for (size_t k = 0; k < classes.size(); ++k) {
+        mwax_plan p = b->inst[classes[k].second[0]];
+        const TuneCache::Entry *e = cache.find(arch, p->n_in, p->L, b->xprec);
+        if (!e || !tile_allowed(b, classes[k].second[0], e->tile) || (e->kchunk > 0 && b->xprec != MWAX_X_INT8))
+            continue;
+        for (int i : classes[k].second) {
+            b->tile[i] = e->tile;
+            b->kchunk[i] = e->kchunk;
+        }
+        cached[k] = true;
+    }
+    std::string sig = "";
+    for (auto &c : classes) {
+        mwax_plan p = b->inst[c.second[0]];
+        sig += std::to_string(p->n_in) + "x" + std::to_string(p->L) + "x" + std::to_string(c.second.size()) + ",";
+    }
+    const int cached_grid = cache.grid(arch, sig, b->xprec);
+    const bool all_cached = std::all_of(cached.begin(), cached.end(), [](bool v) { return v; });
+    if (all_cached && cached_grid > 0) {
+        b->xgrid = std::min(cached_grid, b->xgrid_max);
+        st = layout(b);
+        if (st == MWAX_OK) st = apply_clear_policy(b);
+        return st == MWAX_OK ? ok() : st;
+    }
+
+    // tables sized for the largest candidate (the smallest chunk, the small tile)
+    const std::vector<int> cur_kc = b->kchunk, cur_tile = b->tile;
     b->kchunk.assign(b->n, chunks.back());
+    for (int i = 0; i < b->n; ++i)
+        if (tile_allowed(b, i, kXTileSmall) && xengine_tile_count(b->inst[i]->n_in, kXTileSmall) >
+                                                  xengine_tile_count(b->inst[i]->n_in, b->tile[i]))
+            b->tile[i] = kXTileSmall;
     st = layout(b);
     if (st != MWAX_OK) return st;
-    b->kchunk = saved_kc;
+    b->kchunk = cur_kc;
+    b->tile = cur_tile;
 
     CallTables t;
     build_call(b, d_volts, ld_samples, segs, active, t);
@@ -747,43 +906,38 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
         return MWAX_OK;
     };
 
-    // instance shape classes (inputs, L), heaviest first
-    std::vector<std::pair<int64_t, std::vector<int>>> classes;
-    for (int i = 0; i < b->n; ++i) {
-        mwax_plan p = b->inst[i];
-        bool placed = false;
-        for (auto &c : classes) {
-            mwax_plan q = b->inst[c.second[0]];
-            if (q->n_in == p->n_in && q->L == p->L) {
-                c.second.push_back(i);
-                c.first += p->P * n_samples[i];
-                placed = true;
-            }
-        }
-        if (!placed) classes.push_back({p->P * n_samples[i], {i}});
-    }
-    std::stable_sort(classes.begin(), classes.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
-
     double best = 0.0;
     st = time_x(&best);
     for (int pass = 0; pass < 2 && st == MWAX_OK; ++pass) {
-        for (auto &cl : classes) {
-            const int cur = b->kchunk[cl.second[0]];
-            int pick = cur;
-            for (int kc : chunks) {
-                if (kc == cur) continue;
-                if (kc > 0 && kc >= b->inst[cl.second[0]]->NG) continue;   // same as whole segments
-                for (int i : cl.second) b->kchunk[i] = kc;
-                double ms = 0.0;
-                st = time_x(&ms);
-                if (st != MWAX_OK) break;
-                if (ms < 0.99 * best) {
-                    best = ms;
-                    pick = kc;
+        for (size_t k = 0; k < classes.size() && st == MWAX_OK; ++k) {
+            if (cached[k]) continue;
+            const std::vector<int> &members = classes[k].second;
+            const int i0 = members[0];
+            int pick_kc = b->kchunk[i0], pick_te = b->tile[i0];
+            for (int te : tiles) {
+                if (!tile_allowed(b, i0, te)) continue;
+                for (int kc : chunks) {
+                    if (te == b->tile[i0] && kc == b->kchunk[i0]) continue;
+                    if (kc > 0 && kc >= b->inst[i0]->NG) continue;   // same as whole segments
+                    for (int i : members) {
+                        b->kchunk[i] = kc;
+                        b->tile[i] = te;
+                    }
+                    double ms = 0.0;
+                    st = time_x(&ms);
+                    if (st != MWAX_OK) break;
+                    if (ms < 0.99 * best) {
+                        best = ms;
+                        pick_kc = kc;
+                        pick_te = te;
+                    }
                 }
+                if (st != MWAX_OK) break;
             }
-            for (int i : cl.second) b->kchunk[i] = pick;
-            if (st != MWAX_OK) break;
+            for (int i : members) {
+                b->kchunk[i] = pick_kc;
+                b->tile[i] = pick_te;
+            }
         }
     }
     if (st == MWAX_OK) {
@@ -804,7 +958,15 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
     b->timing = saved_timing;
     if (st != MWAX_OK) {
         b->kchunk = saved_kc;
+        b->tile = saved_tile;
         b->xgrid = saved_grid;
+    } else if (!b->cache_path.empty()) {
+        for (auto &c : classes) {
+            mwax_plan p = b->inst[c.second[0]];
+            cache.put(arch, p->n_in, p->L, b->xprec, b->tile[c.second[0]], b->kchunk[c.second[0]]);
+        }
+        cache.put_grid(arch, sig, b->xprec, b->xgrid);
+        if (!cache.write(b->cache_path)) st = fail(MWAX_E_INVAL, "cannot write the tuning cache %s", b->cache_path.c_str());
     }
     mwax_status st2 = layout(b);
     for (int i = 0; i < b->n; ++i) {
@@ -816,6 +978,34 @@ mwax_status mwax_batch_autotune(mwax_batch b, const int8_t *const *d_volts, cons
     if (st != MWAX_OK) return st;
     if (st2 != MWAX_OK) return st2;
     if (e != hipSuccess) return hip_fail(e, "autotune");
+    return ok();
+}
+
+mwax_status mwax_batch_get_tiles(mwax_batch b, int32_t *tile) {
+    if (check_batch(b) != MWAX_OK) return MWAX_E_INVAL;
+    if (!tile) return fail(MWAX_E_INVAL, "null tile array");
+    for (int i = 0; i < b->n; ++i) tile[i] = b->tile[i];
+    return ok();
+}
+
+mwax_status mwax_batch_set_tiles(mwax_batch b, const int32_t *tile) {
+    if (check_batch(b) != MWAX_OK) return MWAX_E_INVAL;
+    if (!tile) return fail(MWAX_E_INVAL, "null tile array");
+    for (int i = 0; i < b->n; ++i)
+        if (!tile_allowed(b, i, tile[i]))
+            return fail(MWAX_E_INVAL, "tile[%d] = %d: the tile edge is %d or %d (at most %d tiles per channel)", i,
+                        tile[i], kXTile, kXTileSmall, kXBatchMaxTiles);
+    for (int i = 0; i < b->n; ++i)
+        if (b->inst[i]->pending) return fail(MWAX_E_STATE, "instance %d has a pending block", i);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(MWAX_E_DEVICE, "stream synchronisation");
+    b->tile.assign(tile, tile + b->n);
+    mwax_status st = layout(b);
+    return st == MWAX_OK ? ok() : st;
+}
+
+mwax_status mwax_batch_set_tuning_cache(mwax_batch b, const char *path) {
+    if (check_batch(b) != MWAX_OK) return MWAX_E_INVAL;
+    b->cache_path = path ? path : "";
     return ok();
 }
 

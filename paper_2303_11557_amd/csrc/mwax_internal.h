@@ -229,6 +229,10 @@ hipError_t launch_xengine(int xprec, const XArgs &a, hipStream_t s);
 // its integration overwrites them.
 bool xengine_accumulates(int xprec, const XArgs &a);
 int xengine_tile(int xprec);
+// Tile edges of the MFMA X-engine: single plans use kXTile; a batch instance
+// may use either (the autotuner picks).  Lower-triangle tiles per channel:
+constexpr int kXTile = 128, kXTileSmall = 64;
+int xengine_tile_count(int n_in, int te);
 
 // Persistent batched X-engine.  A work item is one 128 x 128 tile of one channel
 // of one segment over a chunk of its row groups, packed in 32 bits:
@@ -250,6 +254,7 @@ struct XDesc {
     int32_t ksplit;         // chunks = ceil(ngrp / kchunk)
     int32_t first;          // as XArgs::first
     int32_t i32;            // as XArgs::i32
+    int32_t te;             // tile edge: kXTile or kXTileSmall
 };
 constexpr int kXBatchMaxDesc = 256;
 constexpr int kXBatchMaxTiles = 256;

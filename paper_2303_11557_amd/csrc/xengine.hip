@@ -34,7 +34,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
-constexpr int kTile = 128;          // tile edge in inputs
+constexpr int kTile = kXTile;       // tile edge in inputs (single-plan launches; a batch
+                                    // instance may take kTileSmall, see xengine_batch)
+constexpr int kTileSmall = kXTileSmall;
 constexpr int kThreads = 256;       // 4 waves
 constexpr int kKG = 4;              // row groups per LDS stage
 
@@ -127,15 +129,26 @@ constexpr int kXG = 2;                      // row groups per stage
 constexpr int kNBuf = 4;                    // stage buffers
 constexpr int kDist = 2;                    // stages copied ahead of the matrix work (< kNBuf)
 constexpr int kBlock = 32 * kRowBytes;      // LDS bytes of 32 rows: [half][row][16 B]
-constexpr int kGroupPitch = kTile / 32 * kBlock;
-constexpr int kPanel = kXG * kGroupPitch;   // one panel (A or B) of a stage
-constexpr int kStage = 2 * kPanel;
-constexpr int kCopiesPerStage = 2 * kXG;    // global -> LDS copies per wave per stage
 static_assert((kNBuf == 2 || kNBuf == 4) && kDist >= 1 && kDist < kNBuf, "ring of 2 or 4 stage buffers");
-// s_waitcnt immediate: vmcnt(copies of the kDist - 1 later stages), lgkmcnt(0)
-constexpr int kWaitCopies = kCopiesPerStage * (kDist - 1);
-static_assert(kWaitCopies < 16, "vmcnt immediate");
-constexpr int kStageWait = kWaitCopies | (7 << 4);
+
+// Stage geometry of a TE x TE tile (TE = 128 or 64).  A 128-edge tile gives each
+// of the four waves 64 x 64 outputs (2 x 2 blocks of 32 x 32) and each wave
+// copies 32 rows of both panels; a 64-edge tile gives each wave one 32 x 32
+// block and each wave copies 32 rows of one panel.
+template <int TE>
+struct TileGeo {
+    static_assert(TE == 128 || TE == 64, "tile edge");
+    static constexpr int MB = TE / 64;                   // 32 x 32 blocks per wave and dimension
+    static constexpr int kGroupPitch = TE / 32 * kBlock;
+    static constexpr int kPanel = kXG * kGroupPitch;     // one panel (A or B) of a stage
+    static constexpr int kStage = 2 * kPanel;
+    static constexpr int kCopiesPerStage = (TE == 128 ? 2 : 1) * kXG;   // copies per wave per stage
+    // s_waitcnt immediate: vmcnt(copies of the kDist - 1 later stages), lgkmcnt(0)
+    static constexpr int kWaitCopies = kCopiesPerStage * (kDist - 1);
+    static_assert(kWaitCopies < 16, "vmcnt immediate");
+    static constexpr int kStageWait = kWaitCopies | (7 << 4);
+};
+constexpr int kStage = TileGeo<kTile>::kStage;          // stage buffers are sized for the larger tile
 
 struct XLds {
     uint8_t *buf[4];   // the first kNBuf are used
@@ -150,17 +163,20 @@ __device__ __align__(16) const uint8_t kZeroGroup[kTile * kRowBytes] = {};
 // workgroup barrier.  The barrier carries no memory fence of its own (a fence
 // would wait for every copy in flight); the wait provides the ordering, and the
 // memory clobber keeps the compiler from moving LDS accesses across it.
+template <int TE>
 __device__ __forceinline__ void stage_barrier() {
-    __builtin_amdgcn_s_waitcnt(kStageWait);
+    __builtin_amdgcn_s_waitcnt(TileGeo<TE>::kStageWait);
     asm volatile("s_barrier" ::: "memory");
 }
 
 // ATOMIC: flush with int64 atomic adds (another workgroup may be flushing other
 // row groups of the same tile at the same time).
-template <int XP, bool ACTIVE, bool ATOMIC = false>
+template <int XP, int TE, bool ACTIVE, bool ATOMIC = false>
 __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &lds, int c, int rowA0, int rowB0,
                                                   int wr, int wc) {
     static_assert(!ATOMIC || XP == MWAX_X_INT8, "atomic flushes are exact for integer partials only");
+    using GEO = TileGeo<TE>;
+    constexpr int MB = GEO::MB, kGroupPitch = GEO::kGroupPitch, kPanel = GEO::kPanel;
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
     constexpr bool INT8 = XP == MWAX_X_INT8;
@@ -168,18 +184,21 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
     const int half = lane >> 5, l32 = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 
-    // Copies: wave w moves rows w * 32 .. w * 32 + 31 of both panels; lane l
-    // takes half l / 32 of row w * 32 + l % 32 and lands at block w, byte l * 16.
+    // Copies: wave w moves rows w * 32 .. w * 32 + 31 of both panels (TE = 128),
+    // or rows (w % 2) * 32 .. + 31 of panel w / 2 (TE = 64); lane l takes half
+    // l / 32 of its row and lands at byte l * 16 of the row's block.
     // Rows past the last input are read from a clamped (valid) address and not
     // cleared: row i of A and column j of B reach only output (i, j), and outputs
     // past the last input are never flushed.
-    const int chalf = lane >> 5, crow = wave * 32 + (lane & 31);
+    const int cblk = TE == 128 ? wave : (wave & 1);          // block within the panel
+    const int cpanel = TE == 128 ? 0 : (wave >> 1) * kPanel;  // TE = 64: the panel this wave copies
+    const int chalf = lane >> 5, crow = cblk * 32 + (lane & 31);
     const uint32_t offA = (uint32_t)min(rowA0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
     const uint32_t offB = (uint32_t)min(rowB0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
     const uint32_t offZ = (uint32_t)crow * kRowBytes + chalf * 16;
     const int64_t gstride = (int64_t)a.n_in * kRowBytes;   // bytes between row groups
     const uint8_t *base = a.chan + ((int64_t)c * a.NG + a.grp0) * gstride;
-    const int ldst = wave * kBlock;
+    const int ldst = cpanel + cblk * kBlock;
     const int nstages = (a.ngrp + kXG - 1) / kXG;
 
     // CHECK: the stage may reach past the segment end (its last stage)
@@ -190,27 +209,33 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             const int g = s * kXG + k;
             const bool in = !CHECK || g < a.ngrp;
             const uint8_t *gb = in ? base + (int64_t)g * gstride : kZeroGroup;
-            __builtin_amdgcn_global_load_lds(gb + (in ? offA : offZ), buf + k * kGroupPitch + ldst, 16, 0, 0);
-            __builtin_amdgcn_global_load_lds(gb + (in ? offB : offZ), buf + kPanel + k * kGroupPitch + ldst, 16, 0,
-                                             0);
+            if constexpr (TE == 128) {
+                __builtin_amdgcn_global_load_lds(gb + (in ? offA : offZ), buf + k * kGroupPitch + ldst, 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(gb + (in ? offB : offZ), buf + kPanel + k * kGroupPitch + ldst, 16,
+                                                 0, 0);
+            } else {
+                // waves 0, 1 copy the A panel, waves 2, 3 the B panel
+                const uint32_t off = in ? (wave < 2 ? offA : offB) : offZ;
+                __builtin_amdgcn_global_load_lds(gb + off, buf + k * kGroupPitch + ldst, 16, 0, 0);
+            }
         }
     };
 
-    acc_t re[2][2], im[2][2];
-    // fragment m of a wave's 64 rows is block 2 * w + m; lane (half, l32) reads
-    // half `half` of its row l32
-    const int fa_off = wr * 2 * kBlock + half * 512 + l32 * 16;
-    const int fb_off = kPanel + wc * 2 * kBlock + half * 512 + l32 * 16;
+    acc_t re[MB][MB], im[MB][MB];
+    // fragment m of a wave's 32 MB rows is block MB * w + m; lane (half, l32)
+    // reads half `half` of its row l32
+    const int fa_off = wr * MB * kBlock + half * 512 + l32 * 16;
+    const int fb_off = kPanel + wc * MB * kBlock + half * 512 + l32 * 16;
     constexpr uint32_t kFlip = INT8 ? 0xffffffffu : 0x80008000u;
 
     // One stage of matrix-core work from one buffer; the fragments of row group
     // k+1 are read while the MFMAs of group k run.
     auto compute = [&](const uint8_t *st) {
-        uint4 fa[2][2], fb[2][2];
+        uint4 fa[2][MB], fb[2][MB];
         auto read = [&](int k, int slot) {
             const int ko = k * kGroupPitch;
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < MB; ++m) {
                 fa[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fa_off + m * kBlock);
                 fb[slot][m] = *reinterpret_cast<const uint4 *>(st + ko + fb_off + m * kBlock);
             }
@@ -220,31 +245,34 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         for (int k = 0; k < kXG; ++k) {
             if (k + 1 < kXG) read(k + 1, (k + 1) & 1);
             const int sl = k & 1;
-            uint4 fb2[2];
+            uint4 fb2[MB];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < MB; ++m) {
                 const uint4 v = fb[sl][m];
                 fb2[m] = make_uint4(v.z ^ kFlip, v.w ^ kFlip, v.x, v.y);
             }
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb2 = 0; nb2 < 2; ++nb2) {
+                for (int nb2 = 0; nb2 < MB; ++nb2) {
                     re[mb][nb2] = T::mma(fa[sl][mb], fb[sl][nb2], re[mb][nb2]);
                     im[mb][nb2] = T::mma(fa[sl][mb], fb2[nb2], im[mb][nb2]);
                 }
         }
-        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);         // reads, group 0
+        // 2 MB reads and 2 MB^2 MFMAs per row group: the reads of group k+1 are
+        // interleaved with the first MFMAs of group k
+        constexpr int kReads = 2 * MB, kMfma = 2 * MB * MB;
+        __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);    // reads, group 0
 #pragma unroll
         for (int k = 0; k + 1 < kXG; ++k) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kReads; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one read of group k+1
             }
-            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+            if constexpr (kMfma > kReads) __builtin_amdgcn_sched_group_barrier(0x008, kMfma - kReads, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);         // MFMAs, last group
+        __builtin_amdgcn_sched_group_barrier(0x008, kMfma, 0);     // MFMAs, last group
     };
 
     // Iteration on stage s held in buffer B: copy stage s + kDist into a buffer
@@ -264,7 +292,7 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         if constexpr (ACTIVE) {
             if (!CHECK || s < s1) compute(lds.buf[B]);
         }
-        stage_barrier();
+        stage_barrier<TE>();
     };
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
@@ -273,7 +301,7 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
 
 #pragma unroll
     for (int b = 0; b < kDist; ++b) copy_stage(b, lds.buf[b], Yes{});
-    stage_barrier();
+    stage_barrier<TE>();
 
     constexpr int kChunkStages = T::kFlushGroups / kXG;
     static_assert(kChunkStages % kNBuf == 0, "flush chunks must start on buffer 0");
@@ -282,9 +310,9 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
         const int s1 = min(nstages, s0 + kChunkStages);
         if constexpr (ACTIVE) {
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb2 = 0; nb2 < 2; ++nb2) {
+                for (int nb2 = 0; nb2 < MB; ++nb2) {
                     re[mb][nb2] = acc_t{};
                     im[mb][nb2] = acc_t{};
                 }
@@ -319,11 +347,11 @@ __device__ __forceinline__ void xengine_tile_loop(const XArgs &a, const XLds &ld
             // integrators instead of adding to them (no read)
             const bool store = a.first && s0 == 0;
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
-                const int RB = wr * 2 + mb;
+            for (int mb = 0; mb < MB; ++mb) {
+                const int RB = wr * MB + mb;
 #pragma unroll
-                for (int nb2 = 0; nb2 < 2; ++nb2) {
-                    const int CB = wc * 2 + nb2;
+                for (int nb2 = 0; nb2 < MB; ++nb2) {
+                    const int CB = wc * MB + nb2;
                     const int n2 = fc0 + CB * 32 + l32;
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -409,13 +437,32 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_mfma(XArgs a) {
     const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
     if constexpr (XP == MWAX_X_INT8) {
         if (a.nks > 1) {
-            if (idle) xengine_tile_loop<XP, false, true>(b, lds, c, rowA0, rowB0, wr, wc);
-            else xengine_tile_loop<XP, true, true>(b, lds, c, rowA0, rowB0, wr, wc);
+            if (idle) xengine_tile_loop<XP, kTile, false, true>(b, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, kTile, true, true>(b, lds, c, rowA0, rowB0, wr, wc);
             return;
         }
     }
-    if (idle) xengine_tile_loop<XP, false>(b, lds, c, rowA0, rowB0, wr, wc);
-    else xengine_tile_loop<XP, true>(b, lds, c, rowA0, rowB0, wr, wc);
+    if (idle) xengine_tile_loop<XP, kTile, false>(b, lds, c, rowA0, rowB0, wr, wc);
+    else xengine_tile_loop<XP, kTile, true>(b, lds, c, rowA0, rowB0, wr, wc);
+}
+
+// One work item of the batched kernel: tile (I, J) of edge TE.  A wave is idle
+// on a diagonal tile above the diagonal, or when all its rows or columns lie past
+// the last input; it still stages data and meets the barriers.
+template <int XP, int TE>
+__device__ __forceinline__ void batch_tile(const XArgs &a, const XLds &lds, int c, int I, int J, int wr, int wc,
+                                           bool atomic) {
+    const int rowA0 = I * TE, rowB0 = J * TE;
+    const bool idle = (I == J && wr < wc) || rowA0 + wr * (TE / 2) >= a.n_in || rowB0 + wc * (TE / 2) >= a.n_in;
+    if constexpr (XP == MWAX_X_INT8) {
+        if (atomic) {
+            if (idle) xengine_tile_loop<XP, TE, false, true>(a, lds, c, rowA0, rowB0, wr, wc);
+            else xengine_tile_loop<XP, TE, true, true>(a, lds, c, rowA0, rowB0, wr, wc);
+            return;
+        }
+    }
+    if (idle) xengine_tile_loop<XP, TE, false>(a, lds, c, rowA0, rowB0, wr, wc);
+    else xengine_tile_loop<XP, TE, true>(a, lds, c, rowA0, rowB0, wr, wc);
 }
 
 // Persistent batched form (see XBatchArgs): each workgroup takes items from the
@@ -455,17 +502,11 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
             a.i32 = xd.i32;
             int I, J;
             tile_ij(t, I, J);
-            const int rowA0 = I * kTile, rowB0 = J * kTile;
-            const bool idle = (I == J && wr < wc) || rowA0 + wr * 64 >= a.n_in || rowB0 + wc * 64 >= a.n_in;
-            if constexpr (XP == MWAX_X_INT8) {
-                if (xd.ksplit > 1) {
-                    if (idle) xengine_tile_loop<XP, false, true>(a, lds, c, rowA0, rowB0, wr, wc);
-                    else xengine_tile_loop<XP, true, true>(a, lds, c, rowA0, rowB0, wr, wc);
-                    continue;
-                }
+            if (xd.te == kTileSmall) {
+                batch_tile<XP, kTileSmall>(a, lds, c, I, J, wr, wc, xd.ksplit > 1);
+            } else {
+                batch_tile<XP, kTile>(a, lds, c, I, J, wr, wc, xd.ksplit > 1);
             }
-            if (idle) xengine_tile_loop<XP, false>(a, lds, c, rowA0, rowB0, wr, wc);
-            else xengine_tile_loop<XP, true>(a, lds, c, rowA0, rowB0, wr, wc);
         }
     }
 }
@@ -598,6 +639,10 @@ __global__ __launch_bounds__(kF32Threads) void xengine_f32(XArgs a) {
 }  // namespace
 
 int xengine_tile(int) { return kTile; }
+int xengine_tile_count(int n_in, int te) {
+    const int t = (n_in + te - 1) / te;
+    return t * (t + 1) / 2;
+}
 
 namespace {
 // Resident workgroups of the single-plan MFMA kernel on the current device.

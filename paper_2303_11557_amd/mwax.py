@@ -28,7 +28,8 @@ EXPORTS = (
     "mwax_set_delays", "mwax_beamform", "mwax_beamform_incoherent", "mwax_integrate_averaged",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
-    "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_set_graph",
+    "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_get_tiles",
+    "mwax_batch_set_tiles", "mwax_batch_set_tuning_cache", "mwax_batch_set_graph",
     "mwax_batch_set_timing", "mwax_batch_kernel_time", "mwax_batch_sync",
     "mwax_stream_create", "mwax_stream_destroy", "mwax_stream_get_info", "mwax_stream_plan",
     "mwax_stream_now", "mwax_stream_acquire", "mwax_stream_copy_in", "mwax_stream_submit",
@@ -134,6 +135,9 @@ def lib():
             "mwax_batch_autotune": [vp, P(vp), P(i64), P(i64), i32],
             "mwax_batch_get_tuning": [vp, P(i32), P(i32)],
             "mwax_batch_set_tuning": [vp, P(i32), i32],
+            "mwax_batch_get_tiles": [vp, P(i32)],
+            "mwax_batch_set_tiles": [vp, P(i32)],
+            "mwax_batch_set_tuning_cache": [vp, ctypes.c_char_p],
             "mwax_batch_set_graph": [vp, i32],
             "mwax_batch_set_timing": [vp, i32],
             "mwax_batch_kernel_time": [vp, i32, P(ctypes.c_double), P(i64)],
@@ -456,11 +460,27 @@ class Batch:
         ptrs, ns, ld = self._arrays(volts, n_samples)
         _check(lib().mwax_batch_run(self.h, ptrs, ns, ld))
 
-    def autotune(self, volts, trials=3):
+    def autotune(self, volts, trials=3, cache=None):
+        """Tune on the given blocks; cache: path of the on-disk tuning cache to
+        consult and update (None: keep the batch's setting)."""
         assert len(volts) == self.n
+        if cache is not None:
+            self.set_tuning_cache(cache)
         ptrs, ns, ld = self._arrays(volts, None)
         _check(lib().mwax_batch_autotune(self.h, ptrs, ns, ld, int(trials)))
         return self.tuning()
+
+    def tiles(self):
+        t = (ctypes.c_int32 * self.n)()
+        _check(lib().mwax_batch_get_tiles(self.h, t))
+        return list(t)
+
+    def set_tiles(self, tiles):
+        assert len(tiles) == self.n
+        _check(lib().mwax_batch_set_tiles(self.h, (ctypes.c_int32 * self.n)(*[int(t) for t in tiles])))
+
+    def set_tuning_cache(self, path):
+        _check(lib().mwax_batch_set_tuning_cache(self.h, None if not path else os.fsencode(path)))
 
     def tuning(self):
         kc = (ctypes.c_int32 * self.n)()

@@ -76,13 +76,16 @@ def run_single(prec, volts, shapes=SHAPES, chunk=CHUNK, calls=CALLS):
 
 
 def run_batch(prec, volts, graph=True, tuning=None, autotune=False, between=None, shapes=SHAPES,
-              chunk=CHUNK, calls=CALLS):
+              chunk=CHUNK, calls=CALLS, tiles=None):
     outs = [[] for _ in shapes]
     volts = volts[:len(shapes)]
     with Batch(cfgs(prec, shapes, chunk)) as b:
         b.set_graph(graph)
         if tuning is not None:
             b.set_tuning(*tuning)
+        if tiles is not None:
+            b.set_tiles(tiles)
+            assert b.tiles() == list(tiles)
         if autotune:
             kc, grid = b.autotune([v[:, :chunk] for v in volts], trials=2)
             log(f"autotuned kchunk={kc} grid={grid}")
@@ -147,6 +150,82 @@ def test_batch_autotune_then_exact(volts, single_int8):
     log("batch int8 autotune")
     got = run_batch("int8", volts, autotune=True)
     assert_same(got, single_int8, "autotuned batch vs single")
+
+
+@pytest.mark.parametrize("kc", [0, 128])
+def test_batch_int8_small_tiles_equal_single_plans(volts, single_int8, kc):
+    # 64 x 64 MFMA tiles (one 32 x 32 block per wave), whole-segment and chunked
+    # items: the same integer sums as the single plans' 128 x 128 tiles
+    log(f"batch int8 tile 64 kchunk={kc}")
+    got = run_batch("int8", volts, tuning=([kc] * len(SHAPES), 0), tiles=[64] * len(SHAPES))
+    assert_same(got, single_int8, f"batch tile 64 kchunk={kc} vs single")
+
+
+def test_batch_fp16_small_tiles_equal_single_plans(volts):
+    # every 32 x 32 output block runs the same MFMA chain over the same row
+    # groups whatever the tile edge, so the FP16 sums are bit-identical too
+    shapes = SHAPES[:3]
+    ref = run_single("fp16", volts, shapes)
+    log("batch fp16 tile 64")
+    got = run_batch("fp16", volts, shapes=shapes, tiles=[64] * len(shapes))
+    assert_same(got, ref, "fp16 batch tile 64 vs single")
+
+
+def test_batch_small_tiles_match_oracle_integer_xengine():
+    # 128, 200 (ragged against 64) and 6 inputs on 64-edge tiles, chunked
+    # items: the oracle's int64 X-engine on the codes the batch wrote
+    shapes = [(64, 32, 256), (100, 128, 64), (3, 1024, 8)]
+    S = 8192
+    vs = [make_volts(20 + i, 2 * t, S) for i, (t, L, T) in enumerate(shapes)]
+    with Batch(cfgs("int8", shapes, S)) as b:
+        b.set_tuning([3] * len(shapes), 0)
+        b.set_tiles([64] * len(shapes))
+        b.run(vs)
+        for i, p in enumerate(b.plans):
+            q = p.read_channelised().cpu().numpy()
+            raw, _ = p.integrate_raw(2)
+            raw = raw.cpu().numpy()
+            L, T = shapes[i][1], shapes[i][2]
+            log(f"oracle int check, tile 64, instance {i} n={2 * shapes[i][0]} L={L} T={T}")
+            ref = oracle.correlate_i64(q, T)
+            assert raw.shape == ref.shape
+            assert np.array_equal(raw, ref)
+
+
+def test_batch_tuning_cache(volts, tmp_path):
+    shapes = [SHAPES[3], SHAPES[4]]                # 128 and 10 inputs
+    vs = [volts[3], volts[4]]
+    cache = tmp_path / "mwax_tuning.txt"
+    with Batch(cfgs("int8", shapes)) as b:
+        with pytest.raises(mwax.MwaxError) as e:
+            b.set_tiles([32, 128])
+        assert e.value.status == mwax.MWAX_E_INVAL
+        kc, grid = b.autotune([v[:, :CHUNK] for v in vs], trials=1, cache=str(cache))
+        tiles = b.tiles()
+    lines = cache.read_text().split("\n")
+    shape_lines = sorted(l.split() for l in lines if l.startswith("shape "))
+    grid_lines = [l.split() for l in lines if l.startswith("grid ")]
+    log(f"tuning cache: {shape_lines} {grid_lines}")
+    assert len(shape_lines) == 2 and len(grid_lines) == 1
+    want = sorted([["shape", shape_lines[0][1], str(2 * t), str(L), str(mwax.X_INT8), str(te), str(k)]
+                   for (t, L, T), te, k in zip(shapes, tiles, kc)])
+    assert shape_lines == want
+    assert int(grid_lines[0][4]) == grid
+    # a second batch takes the cached choices without timing anything: plant a
+    # choice the tuner would not make and check that it is the one in force
+    arch = shape_lines[0][1]
+    planted = [f"shape {arch} {2 * t} {L} {mwax.X_INT8} 64 256" for (t, L, T) in shapes]
+    cache.write_text("garbage line\n" + "\n".join(planted) + f"\n{' '.join(grid_lines[0][:4])} 100\n")
+    outs = [[] for _ in shapes]
+    with Batch(cfgs("int8", shapes)) as b:
+        kc2, grid2 = b.autotune([v[:, :CHUNK] for v in vs], trials=1, cache=str(cache))
+        assert (kc2, grid2, b.tiles()) == ([256, 256], 100, [64, 64])
+        for k in range(CALLS):
+            b.run([v[:, k * CHUNK:(k + 1) * CHUNK] for v in vs])
+            for i, p in enumerate(b.plans):
+                outs[i].append(drain(p, "int8"))
+        b.sync()
+    assert_same(outs, run_single("int8", vs, shapes), "batch on cached tuning vs single")
 
 
 def test_batch_fp16_equals_single_plans(volts):
