@@ -243,6 +243,25 @@ mwax_status mwax_integrate(mwax_plan p, void *d_vis, int32_t max_ints, int32_t *
 mwax_status mwax_integrate_averaged(mwax_plan p, int32_t fscrunch, const float *d_weights, void *d_vis,
                                     int32_t max_ints, int32_t *n_emitted);
 
+/* Averaging inside the X-engine (Sec. 2.6 folded into Sec. 2.5.2): from the
+ * next block on, the plan correlates its fine channels straight into
+ * N = L / fscrunch output channels by the averaging rule of mwax_fscrunch
+ * (offsets |d| <= fscrunch / 2 around each output channel's centre, the
+ * outermost pair at weight 1/2 for even fscrunch, DC left out of the centre
+ * channel; weighted means), so the fine-channel visibilities are never formed
+ * (at L = 6400 and 250 ms integrations, 6.7 GB of integrator traffic per
+ * integration is avoided).  mwax_integrate then emits N channels
+ * ([max_ints][N][P] complex64, or the tile-baseline order over N channels);
+ * mwax_integrate_raw_i64 and mwax_integrate_averaged are refused
+ * (MWAX_E_STATE).  Arithmetic: each fine channel's partial sums over a
+ * segment (INT8: the exact integer sums times s_c^2) are weighted and summed
+ * in FP32, then accumulated across segments in FP64 integrators.  INT8 and
+ * FP16 plans only (MWAX_E_UNSUPPORTED for FP32 plans and for batch or stream
+ * instances); fscrunch must divide L (1 turns it off); allowed before the
+ * first block and after mwax_reset only (MWAX_E_STATE), and kept by
+ * mwax_reset. */
+mwax_status mwax_set_averaging(mwax_plan p, int32_t fscrunch);
+
 /* INT8 plans only: like mwax_integrate in CHAN_TRI order but emits the exact
  * int64 sums, d_vis = [max_ints][L][P][2] int64 (re, im), and, if d_scales is
  * not NULL, the per-channel scales s_c used, [max_ints][L] float32.

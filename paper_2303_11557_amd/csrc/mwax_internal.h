@@ -220,6 +220,25 @@ struct XArgs {
                             // non-atomic flush stores instead of adding
     int32_t i32;            // INT8 integrators are int32 pairs (else int64)
 };
+// Averaging X-engine (plans with mwax_set_averaging): one segment of F-channel
+// output channels, accumulated straight into FP64 integrators [N][P][2].
+struct XAvgArgs {
+    const uint8_t *chan;    // [L][NG][N_in][32 B]
+    int64_t NG;
+    int64_t grp0;           // first group of the segment
+    int32_t ngrp;           // groups in the segment
+    int32_t n_in;
+    int32_t L;
+    int32_t F;              // fine channels per output channel
+    int32_t N;              // output channels, L / F
+    int32_t ntiles;         // 64-edge lower-triangle tiles per channel
+    const float *scales;    // INT8: s_c [L] of the segment's integration; else NULL
+    void *integ;            // this slot's integrators [N][P] (double2)
+    int64_t P;
+    int32_t first;          // the segment starts its integration: store, not add
+};
+hipError_t launch_xengine_avg(int xprec, const XAvgArgs &a, hipStream_t s);
+
 // INT8 launches split every tile's row groups into chunks when that fills the
 // device's resident workgroup slots more evenly (chunks flush with exact int64
 // atomic adds); other precisions run whole segments.

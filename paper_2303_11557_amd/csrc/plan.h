@@ -79,6 +79,7 @@ struct mwax_plan_s {
     // Chunks fill the resident slots of a launch running alone; the stream
     // runtime sets this, because its two lanes fill each other's launch tails.
     bool whole_segments = false;
+    int favg = 1;                   // mwax_set_averaging: fine channels per emitted channel
 
     bool timing = false;
     struct Ev { hipEvent_t a, b; int fam; };

@@ -639,6 +639,27 @@ mwax_status mwax_correlate(mwax_plan p) {
     if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
     if (!p->pending) return fail(MWAX_E_STATE, "no fresh channelised block to correlate");
     for (const Segment &s : p->segs) {
+        if (p->favg > 1) {
+            // averaging X-engine: whole segments, the first one of an integration stores
+            XAvgArgs v{};
+            v.chan = p->chan;
+            v.NG = p->NG;
+            v.grp0 = s.grp0;
+            v.ngrp = (int32_t)s.ngrp;
+            v.n_in = p->n_in;
+            v.L = p->L;
+            v.F = p->favg;
+            v.N = p->L / p->favg;
+            v.ntiles = xengine_tile_count(p->n_in, kXTileSmall);
+            v.scales = p->xprec == MWAX_X_INT8 ? p->scales + (size_t)s.slot * 2 * p->L : nullptr;
+            v.integ = (uint8_t *)p->integ + (size_t)s.slot * p->slot_bytes;
+            v.P = p->P;
+            v.first = s.local0 == 0;
+            hipError_t e = timed(p, 1, [&] { return launch_xengine_avg(p->xprec, v, p->stream); });
+            if (e != hipSuccess) return hip_fail(e, "X-engine launch");
+            p->slot_count[s.slot] += s.nframes;
+            continue;
+        }
         const XArgs a = xengine_args(p, s);
         if (s.local0 == 0 && !p->clear_on_emit && xengine_accumulates(p->xprec, a)) {
             // this launch adds into a slot that was not cleared when it was last emitted
@@ -657,25 +678,27 @@ static mwax_status emit(mwax_plan p, void *d_vis, float *d_scales, int32_t max_i
                         int32_t order, int32_t F = 1, const float *avg_w = nullptr) {
     int32_t n = 0;
     const double post = p->xprec == MWAX_X_FP16 ? std::ldexp(1.0, 2 * fp16_exponent(p->L)) : 1.0;
-    const size_t per_int = order == MWAX_ORDER_TILE_BL ? (size_t)p->d.n_baselines * p->L * 4
+    const int Lout = p->L / p->favg;   // channels held by the integrators as emitted
+    const size_t per_int = order == MWAX_ORDER_TILE_BL ? (size_t)p->d.n_baselines * Lout * 4
                            : order == 3                ? (size_t)(p->L / F) * p->P
-                                                       : (size_t)p->L * p->P;
+                                                       : (size_t)Lout * p->P;
     const size_t esz = order == 2 ? 16 : 8;
+    const bool pre = p->favg > 1;   // averaged in the X-engine: FP64 integrators [L / favg][P]
     while (n < max_ints) {
         const int64_t j = p->next_emit;
         const int slot = (int)(j % p->nslots);
         if (p->slot_owner[slot] != j || p->slot_count[slot] < p->T) break;
         PackArgs a{};
         a.integ = (uint8_t *)p->integ + (size_t)slot * p->slot_bytes;
-        a.is_int = p->xprec == MWAX_X_INT8;
+        a.is_int = p->xprec == MWAX_X_INT8 && !pre;
         a.scales = p->scales + (size_t)slot * 2 * p->L;
         a.post = post;
         a.out = (uint8_t *)d_vis + (size_t)n * per_int * esz;
         a.scales_out = d_scales ? d_scales + (size_t)n * p->L : nullptr;
         a.order = order;
-        a.clear = p->clear_on_emit;
+        a.clear = p->clear_on_emit && !pre;
         a.i32 = p->integ32;
-        a.L = p->L;
+        a.L = pre ? p->L / p->favg : p->L;
         a.n_in = p->n_in;
         a.P = p->P;
         a.F = F;
@@ -708,6 +731,8 @@ mwax_status mwax_integrate_averaged(mwax_plan p, int32_t fscrunch, const float *
     *n_emitted = 0;
     if (fscrunch < 1 || p->L % fscrunch != 0)
         return fail(MWAX_E_INVAL, "fscrunch = %d must divide L = %d", fscrunch, p->L);
+    if (p->favg > 1)
+        return fail(MWAX_E_STATE, "the plan averages in its X-engine (mwax_set_averaging): use mwax_integrate");
     if (max_ints < 0 || (max_ints > 0 && !d_vis)) return fail(MWAX_E_INVAL, "bad output buffer");
     if (((uintptr_t)d_vis & 7) != 0 || ((uintptr_t)d_weights & 3) != 0)
         return fail(MWAX_E_INVAL, "output must be 8-byte and weights 4-byte aligned");
@@ -720,6 +745,8 @@ mwax_status mwax_integrate_raw_i64(mwax_plan p, int64_t *d_vis, float *d_scales,
     if (!n_emitted) return fail(MWAX_E_INVAL, "null n_emitted");
     *n_emitted = 0;
     if (p->xprec != MWAX_X_INT8) return fail(MWAX_E_UNSUPPORTED, "raw int64 output exists for INT8 plans only");
+    if (p->favg > 1)
+        return fail(MWAX_E_STATE, "the plan averages in its X-engine (mwax_set_averaging): no integer sums are kept");
     if (max_ints < 0 || (max_ints > 0 && !d_vis)) return fail(MWAX_E_INVAL, "bad output buffer");
     if (((uintptr_t)d_vis & 15) != 0) return fail(MWAX_E_INVAL, "output must be 16-byte aligned");
     return emit(p, d_vis, d_scales, max_ints, n_emitted, 2);
@@ -808,6 +835,25 @@ mwax_status mwax_reset(mwax_plan p) {
     p->pending = false;
     p->have_block = false;
     p->segs.clear();
+    return ok();
+}
+
+mwax_status mwax_set_averaging(mwax_plan p, int32_t fscrunch) {
+    if (check_plan(p) != MWAX_OK) return MWAX_E_INVAL;
+    if (fscrunch < 1 || p->L % fscrunch != 0)
+        return fail(MWAX_E_INVAL, "fscrunch = %d must divide L = %d", fscrunch, p->L);
+    if (fscrunch > 1 && p->xprec == MWAX_X_FP32)
+        return fail(MWAX_E_UNSUPPORTED, "averaging in the X-engine runs on the matrix cores (INT8 or FP16 plans)");
+    if (p->in_batch) return fail(MWAX_E_UNSUPPORTED, "batch and stream instances do not average in their X-engine");
+    if (fscrunch > 1 && xengine_tile_count(p->n_in, kXTileSmall) * (int64_t)(p->L / fscrunch) > INT32_MAX)
+        return fail(MWAX_E_UNSUPPORTED, "too many work items");
+    // the FP64 output-channel integrators must fit a slot
+    if (fscrunch > 1 && (size_t)(p->L / fscrunch) * (size_t)p->P * 16 > p->slot_bytes)
+        return fail(MWAX_E_UNSUPPORTED, "averaged integrators (%d channels) exceed the plan's slots", p->L / fscrunch);
+    const bool fresh = p->g_chan == 0 && !p->pending &&
+                       std::all_of(p->slot_owner.begin(), p->slot_owner.end(), [](int64_t o) { return o == -1; });
+    if (!fresh) return fail(MWAX_E_STATE, "averaging is chosen before the first block (or after mwax_reset)");
+    p->favg = fscrunch;
     return ok();
 }
 

@@ -26,6 +26,7 @@ EXPORTS = (
     "mwax_channelise", "mwax_load_channelised", "mwax_read_channelised", "mwax_correlate",
     "mwax_integrate", "mwax_integrate_raw_i64", "mwax_set_scales", "mwax_auto_scales", "mwax_get_scales",
     "mwax_set_delays", "mwax_beamform", "mwax_beamform_incoherent", "mwax_integrate_averaged",
+    "mwax_set_averaging",
     "mwax_reset", "mwax_sync", "mwax_set_timing", "mwax_kernel_time", "mwax_last_error",
     "mwax_batch_create", "mwax_batch_destroy", "mwax_batch_plan", "mwax_batch_run",
     "mwax_batch_autotune", "mwax_batch_get_tuning", "mwax_batch_set_tuning", "mwax_batch_get_tiles",
@@ -123,6 +124,7 @@ def lib():
             "mwax_set_delays": [vp, vp, i64, i64, ctypes.c_double],
             "mwax_beamform": [vp, vp, i32, vp, i64, P(i64)],
             "mwax_integrate_averaged": [vp, i32, vp, vp, i32, P(i32)],
+            "mwax_set_averaging": [vp, i32],
             "mwax_beamform_incoherent": [vp, i32, i32, vp, i64, P(i64)],
             "mwax_reset": [vp],
             "mwax_sync": [vp],
@@ -223,6 +225,7 @@ class Plan:
         self.P = d.n_pairs
         self.T = d.spectra_per_int
         self.xprec = cfg.xprec
+        self.favg = 1                 # set_averaging: fine channels per emitted channel
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -304,19 +307,26 @@ class Plan:
         _check(lib().mwax_correlate(self.h))
 
     def integrate(self, max_ints=1, order="tri", out=None):
-        """Emit up to max_ints completed integrations -> complex64 tensor [n][...]."""
+        """Emit up to max_ints completed integrations -> complex64 tensor [n][...]
+        (over L / fscrunch channels after set_averaging(fscrunch))."""
         t = self.torch
         o = _ORDER[order] if isinstance(order, str) else int(order)
+        nc = self.L // self.favg
+        shape = (max_ints, nc, self.P) if o == ORDER_CHAN_TRI else (max_ints, self.dims.n_baselines, nc, 4)
         if out is None:
-            if o == ORDER_CHAN_TRI:
-                shape = (max_ints, self.L, self.P)
-            else:
-                shape = (max_ints, self.dims.n_baselines, self.L, 4)
             out = t.empty(shape, dtype=t.complex64, device="cuda")
+        assert out.is_cuda and out.dtype == t.complex64 and out.is_contiguous()
+        assert tuple(out.shape[1:]) == shape[1:] and out.shape[0] >= max_ints
         n = ctypes.c_int32()
         _check(lib().mwax_integrate(self.h, ctypes.c_void_p(out.data_ptr()), max_ints,
                                     ctypes.byref(n), o))
         return out[: n.value]
+
+    def set_averaging(self, fscrunch):
+        """Average by fscrunch inside the X-engine from the next block on (Sec. 2.6;
+        INT8 and FP16 plans, before the first block or after reset)."""
+        _check(lib().mwax_set_averaging(self.h, int(fscrunch)))
+        self.favg = int(fscrunch)
 
     def integrate_averaged(self, fscrunch, max_ints=1, weights=None, out=None):
         """Emit completed integrations averaged by fscrunch (Sec. 2.6) in the same

@@ -229,3 +229,89 @@ def test_integrate_averaged_equals_averaging_of_the_visibilities(prec, Lc, F):
     ww = oracle.apply_weights(want, w.astype(np.float64))
     assert np.max(rel_frob(outs[True], ww)) < 1e-6
     assert np.array_equal(outs[True][:, :, 3], outs[False][:, :, 3])
+
+
+@pytest.mark.parametrize("prec,Lc,F,n_tiles", [("int8", L, 200, 3), ("int8", L, 50, 40), ("int8", L, 5, 3),
+                                               ("fp16", L, 50, 3), ("int8", 1024, 8, 40), ("fp16", 128, 4, 40),
+                                               ("int8", 128, 1, 3)])
+def test_x_engine_averaging_equals_averaging_of_the_visibilities(prec, Lc, F, n_tiles):
+    # a plan that averages inside its X-engine (mwax_set_averaging) emits what
+    # the oracle's averaging of the same plan's exact visibilities gives, to
+    # FP32 accumulation; the block comes in two calls that split an
+    # integration, so segments accumulate into the FP64 integrators
+    n = 2 * n_tiles
+    T = 12 if Lc == L else 40
+    S = 3 * T * Lc
+    call = S // 2                                 # 1.5 integrations per call
+    v = synth.gaussian_volts(n, S, seed=700 + Lc + F + n, sources=[synth.Source(4.0, Lc // 5)], L=Lc)
+    d = torch.from_numpy(v).cuda()
+    cfg = make_config(n_tiles, L=Lc, T=T, xprec=prec, max_samples=call)
+    with Plan(cfg) as p:
+        for k in range(2):
+            p.channelise(d[:, k * call:(k + 1) * call])
+            p.correlate()
+        if prec == "int8":
+            raw, sc = p.integrate_raw(3)
+            exact = (raw.cpu().numpy()[..., 0] + 1j * raw.cpu().numpy()[..., 1]) * \
+                (sc.cpu().numpy().astype(np.float64) ** 2)[:, :, None]
+        else:
+            exact = p.integrate(3).cpu().numpy().astype(np.complex128)
+    with Plan(cfg) as p:
+        p.set_averaging(F)
+        for k in range(2):
+            p.channelise(d[:, k * call:(k + 1) * call])
+            p.correlate()
+        got = p.integrate(3).cpu().numpy().astype(np.complex128)
+    want = oracle.fscrunch(exact, F)
+    assert got.shape == want.shape == (3, Lc // F, n * (n + 1) // 2)
+    err = np.max(rel_frob(got, want))
+    log(f"X-engine averaging {prec} L={Lc} F={F} n={n}: max rel. Frobenius {err:.3g}")
+    assert err < 2e-6
+    autos = [a * (a + 1) // 2 + a for a in range(n)]
+    assert np.all(np.abs(got[:, :, autos].imag) <= 1e-6 * np.abs(got[:, :, autos].real) + 1e-30)
+
+
+def test_x_engine_averaging_tile_order_and_errors():
+    n_tiles, Lc, T, F = 4, 256, 20, 4
+    n = 2 * n_tiles
+    S = T * Lc
+    v = synth.gaussian_volts(n, S, seed=730, sources=[synth.Source(4.0, 9)], L=Lc)
+    d = torch.from_numpy(v).cuda()
+    cfg = make_config(n_tiles, L=Lc, T=T, xprec="int8", max_samples=S)
+    with Plan(cfg) as p:
+        p.set_averaging(F)
+        p.channelise(d)
+        p.correlate()
+        tri = p.integrate(1, order="tri")
+    with Plan(cfg) as p:
+        p.set_averaging(F)
+        p.channelise(d)
+        p.correlate()
+        tb = p.integrate(1, order="tile_bl").cpu().numpy()
+        for call in (lambda: p.integrate_raw(1), lambda: p.integrate_averaged(2, 1)):
+            with pytest.raises(mwax.MwaxError) as e:
+                call()
+            assert e.value.status == mwax.MWAX_E_STATE
+        with pytest.raises(mwax.MwaxError) as e:
+            p.set_averaging(2)                           # not before the first block
+        assert e.value.status == mwax.MWAX_E_STATE
+        p.reset()
+        with pytest.raises(mwax.MwaxError) as e:
+            p.set_averaging(3)                           # 3 does not divide 256
+        assert e.value.status == mwax.MWAX_E_INVAL
+        p.set_averaging(2)
+        assert p.favg == 2
+    # the tile-baseline order over L / F channels holds the same numbers
+    tri = tri.cpu().numpy()[0]
+    for a in range(n_tiles):
+        for b in range(a + 1):
+            bl = a * (a + 1) // 2 + b
+            for p1 in range(2):
+                for p2 in range(2):
+                    n1, n2 = 2 * a + p1, 2 * b + p2
+                    want = tri[:, n1 * (n1 + 1) // 2 + n2] if n1 >= n2 else np.conj(tri[:, n2 * (n2 + 1) // 2 + n1])
+                    assert np.array_equal(tb[0, bl, :, 2 * p1 + p2], want)
+    with Plan(make_config(2, L=Lc, T=T, xprec="fp32", max_samples=S)) as p:
+        with pytest.raises(mwax.MwaxError) as e:
+            p.set_averaging(F)
+        assert e.value.status == mwax.MWAX_E_UNSUPPORTED
