@@ -176,3 +176,38 @@ def test_stream_full_shape_sampled():
         jl = j - 4                     # integration within the second block
         check_int8(g, host[:, jl * T * L:jl * T * L + 131072], host[sel], sel, L, T, jl,
                    f"stream channel 0 integration {j}")
+
+
+def test_x_engine_averaging_full_shape_sampled():
+    """The 40 kHz / 250 ms mode at full shape: 256 tiles, 6,400 channels, one
+    1 s call (four integrations of 50 spectra), averaged by 200 inside the
+    X-engine (every 64-edge tile of the 512 inputs, ragged ones included).
+    Sampled pairs (both halves of several tiles) against the oracle's integer
+    X-engine on the GPU's own codes, scaled and averaged in FP64."""
+    n_tiles, L, F, tau = 256, 6400, 200, 0.25
+    n_in = 2 * n_tiles
+    S = int(F_S)
+    T = int(round(tau * F_S / L))
+    sel = [0, 1, 2, 63, 64, 100, 130, 200, 257, 330, 400, 460, 510, 511]
+    cols = torch.tensor(pair_cols(sel), device="cuda")
+    s = np.full(L, 5.0 * np.sqrt(L * 64.0) / 127.0, np.float32) * (1.0 + 0.05 * np.cos(np.arange(L) / 97.0)).astype(np.float32)
+    d = torch.empty((n_in, S, 2), dtype=torch.int8, device="cuda")
+    synth.device_volts(d, seed=synth.MWAX_SEED + 6, sources=[synth.Source(3.0, 1234)], L=L)
+    with mwax.Plan(make_config(n_tiles, L=L, int_time_s=tau, xprec="int8", max_samples=S)) as p:
+        p.set_scales(s)
+        p.set_averaging(F)
+        p.channelise(d)
+        codes = p.read_channelised().index_select(2, torch.tensor(sel, device="cuda")).cpu().numpy()
+        p.correlate()
+        got = p.integrate(4).index_select(2, cols).cpu().numpy().astype(np.complex128)
+    log(f"averaging full shape: {got.shape} sampled")
+    assert got.shape == (4, L // F, len(cols))
+    raw = oracle.correlate_i64(codes, T)                       # [4][L][pairs of sel][2]
+    exact = (raw[..., 0] + 1j * raw[..., 1]) * (s.astype(np.float64) ** 2)[None, :, None]
+    want = oracle.fscrunch(exact, F)
+    err = np.abs(got - want) / np.sqrt(np.mean(np.abs(want) ** 2, axis=2, keepdims=True))
+    log(f"averaging full shape: max error {err.max():.3g} of each channel's rms")
+    # the FP32 sum of F + 1 weighted channel terms rounds at most F + 1 times by
+    # 2^-24 of a running sum no larger than the sum of magnitudes, which the
+    # autos that set each channel's rms bound (|V_ab| <= sqrt(V_aa V_bb))
+    assert err.max() < (F + 1) * 2.0 ** -24
