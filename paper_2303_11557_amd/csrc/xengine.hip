@@ -135,16 +135,17 @@ static_assert((kNBuf == 2 || kNBuf == 4) && kDist >= 1 && kDist < kNBuf, "ring o
 // of the four waves 64 x 64 outputs (2 x 2 blocks of 32 x 32) and each wave
 // copies 32 rows of both panels; a 64-edge tile gives each wave one 32 x 32
 // block and each wave copies 32 rows of one panel.
-template <int TE>
+template <int TE, int DIST = kDist>
 struct TileGeo {
     static_assert(TE == 128 || TE == 64, "tile edge");
+    static_assert(DIST >= 1 && DIST < kNBuf, "copies run at most kNBuf - 1 stages ahead");
     static constexpr int MB = TE / 64;                   // 32 x 32 blocks per wave and dimension
     static constexpr int kGroupPitch = TE / 32 * kBlock;
     static constexpr int kPanel = kXG * kGroupPitch;     // one panel (A or B) of a stage
     static constexpr int kStage = 2 * kPanel;
     static constexpr int kCopiesPerStage = (TE == 128 ? 2 : 1) * kXG;   // copies per wave per stage
-    // s_waitcnt immediate: vmcnt(copies of the kDist - 1 later stages), lgkmcnt(0)
-    static constexpr int kWaitCopies = kCopiesPerStage * (kDist - 1);
+    // s_waitcnt immediate: vmcnt(copies of the DIST - 1 later stages), lgkmcnt(0)
+    static constexpr int kWaitCopies = kCopiesPerStage * (DIST - 1);
     static_assert(kWaitCopies < 16, "vmcnt immediate");
     static constexpr int kStageWait = kWaitCopies | (7 << 4);
 };
@@ -163,9 +164,9 @@ __device__ __align__(16) const uint8_t kZeroGroup[kTile * kRowBytes] = {};
 // workgroup barrier.  The barrier carries no memory fence of its own (a fence
 // would wait for every copy in flight); the wait provides the ordering, and the
 // memory clobber keeps the compiler from moving LDS accesses across it.
-template <int TE>
+template <int TE, int DIST = kDist>
 __device__ __forceinline__ void stage_barrier() {
-    __builtin_amdgcn_s_waitcnt(TileGeo<TE>::kStageWait);
+    __builtin_amdgcn_s_waitcnt(TileGeo<TE, DIST>::kStageWait);
     asm volatile("s_barrier" ::: "memory");
 }
 
@@ -528,10 +529,16 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_batch(XBatchArgs b) {
 // complement of the per-channel kernel, so each channel's partials are its
 // exact sums before scaling.
 // ---------------------------------------------------------------------------
+// Copies run three stages ahead here (two in the per-channel kernel): a work
+// item's stages are short (4 MFMAs per wave at 250 ms integrations) and every
+// workgroup of a launch is resident at once, so the copies in flight are what
+// hides the L2 latency.
+constexpr int kAvgDist = 3;
+
 template <int XP>
 __global__ __launch_bounds__(kThreads, 4) void xengine_avg(XAvgArgs a) {
     constexpr int TE = kTileSmall;
-    using GEO = TileGeo<TE>;
+    using GEO = TileGeo<TE, kAvgDist>;
     constexpr int kGroupPitch = GEO::kGroupPitch, kPanel = GEO::kPanel;
     using T = MfmaT<XP>;
     using acc_t = typename T::acc_t;
@@ -552,14 +559,20 @@ __global__ __launch_bounds__(kThreads, 4) void xengine_avg(XAvgArgs a) {
     const int wr = wave >> 1, wc = wave & 1;
     const bool active = !((I == J && wr < wc) || rowA0 + wr * 32 >= a.n_in || rowB0 + wc * 32 >= a.n_in);
 
-    // the fine channels of o: offsets d = -h .. h (DC skipped in the centre one)
+    // the fine channels of o: offsets d = -h .. h (DC skipped in the centre one),
+    // channel (L/2 + (o - N/2) F + d) mod L.  They are walked with cursors: no
+    // division or remainder in the loop, whose scalar work per stage is what
+    // bounds a stage of four MFMAs per wave.
     const int h = a.F / 2, oc = a.N / 2;
     const bool even = (a.F & 1) == 0, centre = a.F > 1 && o == oc;
     const int nch = 2 * h + 1 - (centre ? 1 : 0);
-    const float wsum = centre ? (float)(a.F - 1) : (float)a.F;
-    const int cbase = a.L / 2 + (o - oc) * a.F;
-    auto offset_of = [&](int ci) { return -h + ci + (centre && ci >= h ? 1 : 0); };
-    auto channel_of = [&](int ci) { return ((cbase + offset_of(ci)) % a.L + a.L) % a.L; };
+    const float inv_wsum = 1.0f / (centre ? (float)(a.F - 1) : (float)a.F);
+    const int c_first = ((a.L / 2 + (o - oc) * a.F - h) % a.L + a.L) % a.L;
+    // next channel after c at offset d (skipping DC in the centre channel)
+    auto next_channel = [&](int c, int d) {
+        int n = c + ((centre && d == -1) ? 2 : 1);
+        return n >= a.L ? n - a.L : n;
+    };
 
     // copies: waves 0, 1 move 32 rows each of the A panel, waves 2, 3 of the B panel
     const int cblk = wave & 1, cpanel = (wave >> 1) * kPanel;
@@ -568,19 +581,36 @@ __global__ __launch_bounds__(kThreads, 4) void xengine_avg(XAvgArgs a) {
     const uint32_t offR = (uint32_t)min(rowC0 + crow, a.n_in - 1) * kRowBytes + chalf * 16;
     const uint32_t offZ = (uint32_t)crow * kRowBytes + chalf * 16;
     const int64_t gstride = (int64_t)a.n_in * kRowBytes;
+    const int64_t cstride = a.NG * gstride;       // bytes between channels
     const int ldst = cpanel + cblk * kBlock;
     const int spc = (a.ngrp + kXG - 1) / kXG;     // stages per channel
     const int nst = nch * spc;
 
-    auto copy_stage = [&](int s, uint8_t *buf) {
-        const int ci = s / spc, ls = s - ci * spc;
-        const uint8_t *cb = a.chan + ((int64_t)channel_of(min(ci, nch - 1)) * a.NG + a.grp0) * gstride;
+    // copy cursor: channel index, its channel and offset, stage within it, and the
+    // address of the stage's first row group
+    int cp_ci = 0, cp_c = c_first, cp_d = -h, cp_g = 0;
+    if (centre && cp_d == 0) cp_d = 1;            // (h = 0 only when F = 1: no centre rule)
+    const uint8_t *cp_base = a.chan + ((int64_t)cp_c * a.NG + a.grp0) * gstride;
+    const uint8_t *cp_src = cp_base;
+    const int64_t stage_bytes = (int64_t)kXG * gstride;
+    auto copy_next = [&](uint8_t *buf) {
+        const bool live = cp_ci < nch;
 #pragma unroll
         for (int k = 0; k < kXG; ++k) {
-            const int g = ls * kXG + k;
-            const bool in = s < nst && g < a.ngrp;
-            const uint8_t *src = in ? cb + (int64_t)g * gstride + offR : kZeroGroup + offZ;
+            const bool in = live && cp_g + k < a.ngrp;
+            const uint8_t *src = in ? cp_src + k * gstride + offR : kZeroGroup + offZ;
             __builtin_amdgcn_global_load_lds(src, buf + k * kGroupPitch + ldst, 16, 0, 0);
+        }
+        cp_g += kXG;
+        cp_src += stage_bytes;
+        if (cp_g >= a.ngrp) {
+            cp_g = 0;
+            ++cp_ci;
+            const int nc = next_channel(cp_c, cp_d);
+            cp_base += (int64_t)(nc - cp_c) * cstride;
+            cp_src = cp_base;
+            cp_c = nc;
+            cp_d += (centre && cp_d == -1) ? 2 : 1;
         }
     };
 
@@ -609,35 +639,58 @@ __global__ __launch_bounds__(kThreads, 4) void xengine_avg(XAvgArgs a) {
             im = T::mma(fa[k & 1], fb2, im);
         }
     };
-    // after channel ci's last stage: its partials, scaled and weighted, into the sums
-    auto finish_channel = [&](int ci) {
-        const int d = offset_of(ci);
-        float coef = (even && (d == -h || d == h) ? 0.5f : 1.0f) / wsum;
-        if (a.scales) {
-            const float sc = a.scales[channel_of(ci)];
-            coef *= sc * sc;
-        }
+    // Weight of every channel index ci (weight / weight total, times s_c^2): a
+    // table held across the lanes, lane l holding ci = w0 + 64 t + l (t < 4) of
+    // the window of 256 indices from w0, read with v_readlane when a channel is
+    // done -- no memory access in the loop, whose vector-memory counter belongs
+    // to the copies in flight.
+    float ctab[4];
+    auto load_window = [&](int w0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            sr[r] = fmaf(coef, (float)re[r], sr[r]);
-            si[r] = fmaf(coef, (float)im[r], si[r]);
+        for (int t = 0; t < 4; ++t) {
+            const int ci = w0 + 64 * t + lane;
+            const int d = -h + ci + (centre && ci >= h ? 1 : 0);
+            const int c = (((a.L / 2 + (o - oc) * a.F + d) % a.L) + a.L) % a.L;
+            float coef = (even && (d == -h || d == h) ? 0.5f : 1.0f) * inv_wsum;
+            if (a.scales && ci < nch) {
+                const float sc = a.scales[c];
+                coef *= sc * sc;
+            }
+            ctab[t] = coef;
         }
-        re = acc_t{};
-        im = acc_t{};
     };
+    load_window(0);
+    // compute cursor: channel index and the stage within the channel
+    int cm_ci = 0, cm_ls = 0;
     auto iteration = [&](int s, auto b_c) {
         constexpr int B = decltype(b_c)::value;
-        copy_stage(s + kDist, bufs[(B + kDist) % kNBuf]);
-        if (s < nst && active) {
-            compute(bufs[B]);
-            if ((s + 1) % spc == 0) finish_channel(s / spc);
+        copy_next(bufs[(B + kAvgDist) % kNBuf]);
+        if (s < nst) {
+            if (active) compute(bufs[B]);
+            if (++cm_ls == spc) {
+                // the channel's partials, scaled and weighted, into the sums
+                if (active) {
+                    const int t = (cm_ci >> 6) & 3;
+                    const float tv = t == 0 ? ctab[0] : (t == 1 ? ctab[1] : (t == 2 ? ctab[2] : ctab[3]));
+                    const float coef = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tv), cm_ci & 63));
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        sr[r] = fmaf(coef, (float)re[r], sr[r]);
+                        si[r] = fmaf(coef, (float)im[r], si[r]);
+                    }
+                    re = acc_t{};
+                    im = acc_t{};
+                }
+                cm_ls = 0;
+                if ((++cm_ci & 255) == 0 && cm_ci < nch) load_window(cm_ci);
+            }
         }
-        stage_barrier<TE>();
+        stage_barrier<TE, kAvgDist>();
     };
 
 #pragma unroll
-    for (int b = 0; b < kDist; ++b) copy_stage(b, bufs[b]);
-    stage_barrier<TE>();
+    for (int b = 0; b < kAvgDist; ++b) copy_next(bufs[b]);
+    stage_barrier<TE, kAvgDist>();
     for (int s = 0; s < nst; s += kNBuf) {
         iteration(s, std::integral_constant<int, 0>{});
         iteration(s + 1, std::integral_constant<int, 1>{});

@@ -77,9 +77,9 @@ def kernel_key(name):
         return "beamform_coherent"
     if s.startswith("incoherent_kernel"):
         return "beamform_incoherent"
-    m = re.match(r"xengine_(mfma|batch)<(\d)>", s)
+    m = re.match(r"xengine_(mfma|batch|avg)<(\d)>", s)
     if m:
-        return f"xengine_{'batch_' if m.group(1) == 'batch' else ''}{PREC[m.group(2)]}"
+        return f"xengine_{'' if m.group(1) == 'mfma' else m.group(1) + '_'}{PREC[m.group(2)]}"
     if s.startswith("xengine_f32"):
         return "xengine_fp32"
     if s.startswith("pack_"):
