@@ -126,28 +126,22 @@ struct Elem<MWAX_X_FP32> { static constexpr int ES = 4; };
 // epilogue: lane d holds the signed bins d + 400 j (j = -8 .. 7), so its gains
 // exp(-2 pi i ((d + 400 j) d_s / L + phi)) are b w^j with b, w from two sincos.
 template <int XP, bool STATS, bool DELAY>
-__global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
+__global__ __launch_bounds__(kT, 2) void fft6400_kernel(FArgs a) {
     __shared__ float2 blk[kN1 * kPitch];
     constexpr int ES = Elem<XP>::ES;
     const int r = threadIdx.x;
     const int64_t items = (int64_t)a.n_in * a.nframes;
 
-    // Per-lane twiddles, the same for every frame this lane transforms, kept as
-    // factors: W_6400^(r k1) = W^(r c) W^(5 r d) for k1 = c + 5 d, and
-    // W_256^(ra k) = W_256^(ra e) W_256^(4 ra f) for k = e + 4 f (W = W_6400).
-    float2 p1[5], q1[5];
+    // Per-lane twiddles, the same for every frame this lane transforms:
+    // W_6400^(r k1) (k1 = 1 .. 24) after pass 1 and W_256^(ra k) = W_6400^(25 ra k)
+    // (k = 1 .. 15) after the DFTs of pass 2, one complex multiply per bin.
+    float2 t1[kN1];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        p1[j] = a.tw[(r * j) % kL];
-        q1[j] = a.tw[(5 * r * j) % kL];
-    }
+    for (int k1 = 1; k1 < kN1; ++k1) t1[k1] = a.tw[r * k1];           // r k1 < 6400
     const int ra = r & 15;            // pass-2 column of both of this lane's DFTs
-    float2 p2[4], q2[4];
+    float2 t2[16];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        p2[j] = a.tw[(25 * ra * j) % kL];
-        q2[j] = a.tw[(100 * ra * j) % kL];
-    }
+    for (int k = 1; k < 16; ++k) t2[k] = a.tw[25 * ra * k];           // 25 ra k < 6400
 
     float acc[STATS ? 32 : 1];
 #pragma unroll
@@ -184,8 +178,7 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
         dft25(v);
 #pragma unroll
         for (int k1 = 1; k1 < kN1; ++k1) {
-            if (k1 % 5) v[k1] = cmul(v[k1], p1[k1 % 5]);
-            if (k1 / 5) v[k1] = cmul(v[k1], q1[k1 / 5]);
+            v[k1] = cmul(v[k1], t1[k1]);
         }
         __syncthreads();   // the previous frame's pass 3 has read blk
 #pragma unroll
@@ -201,8 +194,7 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
             dft_regs<16>(w);
 #pragma unroll
             for (int k = 1; k < 16; ++k) {
-                if (k % 4) w[k] = cmul(w[k], p2[k % 4]);
-                if (k / 4) w[k] = cmul(w[k], q2[k / 4]);
+                w[k] = cmul(w[k], t2[k]);
             }
 #pragma unroll
             for (int k = 0; k < 16; ++k) col[16 * k] = w[k];
@@ -232,6 +224,8 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
             if (d < kNd) {
                 const int k1 = d % kN1, k2a = d / kN1;
                 const float2 *row = blk + k1 * kPitch + 16 * k2a;
+                uint8_t *drow = a.mid + (((n * a.mid_frames) + a.frame0 + m) * kL + d) * 2 * ES;
+                const float *srow = a.inv_s + d;
                 float2 z[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) z[q] = row[q];
@@ -253,10 +247,12 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
                     if constexpr (STATS) {
                         acc[slot * 16 + k2b] += X.x * X.x + X.y * X.y;
                     } else {
-                        const int c = (d + 400 * k2b + kL / 2) % kL;
-                        uint8_t *dst = a.mid + (((n * a.mid_frames) + a.frame0 + m) * kL + c) * 2 * ES;
+                        // channel (d + 400 k2b + L/2) mod L = d + 400 ((k2b + 8) mod 16), as
+                        // d < 400: a compile-time offset from the lane's first channel
+                        const int co = 400 * ((k2b + 8) & 15);
+                        uint8_t *dst = drow + co * 2 * ES;
                         if constexpr (XP == MWAX_X_INT8) {
-                            const float s = a.inv_s[c];
+                            const float s = srow[co];
                             const uint32_t br = quant8_bits(X.x, s) & 0xffu, bi = quant8_bits(X.y, s) & 0xffu;
                             *reinterpret_cast<uint16_t *>(dst) = (uint16_t)(br | (bi << 8));
                         } else if constexpr (XP == MWAX_X_FP16) {
@@ -289,57 +285,120 @@ __global__ __launch_bounds__(kT) void fft6400_kernel(FArgs a) {
 
 // Frame-major spectra [input][frame][channel][re, im] (elements of ES bytes) ->
 // channel-major row groups [channel][group][input][32 B] (the row layout of
-// row_re_off / row_im_gap).  A workgroup moves one tile of G frames (one row
-// group) x 64 channels x 16 inputs = 32 KB through LDS: 16-byte loads along the
-// channel axis, 16-byte stores of whole half rows, 512 contiguous bytes per
-// channel.  Frames past the segment and inputs past n_in read as zeros; rows of
+// row_re_off / row_im_gap).  A workgroup moves one row group (G frames) x 64
+// channels x 32 inputs = 64 KB.  Loads: 16 bytes per lane along the channels of
+// one (input, frame), stored as they are into an LDS image [input][frame]
+// [channel] (each input's block padded by 16 bytes).  Then lane (input, channel
+// quad) reads the G x 4 samples of its quad, regroups them in registers into the
+// four 32-byte rows of (channel, input) and stores them; the 32 lanes of a
+// half-wave hold 32 consecutive inputs, so the rows of a channel go out as 1 KB
+// runs.  Frames past the segment and inputs past n_in read as zeros; rows of
 // inputs past n_in are not written.
+constexpr int kCtChannels = 64, kCtInputs = 32;
+
+// Bytes of {hi, lo} picked by sel (v_perm_b32: selector 0-3 picks bytes of lo,
+// 4-7 bytes of hi).
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
 template <int ES>
 __global__ __launch_bounds__(256) void corner_turn_kernel(CornerArgs a) {
-    constexpr int G = 16 / ES, CB = 64, NB = 16;
-    constexpr int UPF = CB * 2 * ES / 16;           // 16-byte units per (input, frame)
-    constexpr int CPU = 16 / (2 * ES);              // channels per unit
-    __shared__ __align__(16) uint8_t img[CB * NB * kRowBytes];
+    constexpr int G = 16 / ES, CB = kCtChannels, NB = kCtInputs;
+    constexpr int FB = CB * 2 * ES;            // bytes of one (input, frame)
+    constexpr int NPITCH = G * FB + 16;        // bytes of one input's block
+    constexpr int UPF = FB / 16;               // 16-byte units per (input, frame)
+    __shared__ __align__(16) uint8_t img[NB * NPITCH];
     const int g = blockIdx.x, c0 = blockIdx.y * CB, n0 = blockIdx.z * NB;
     const int tid = threadIdx.x;
     const int fvalid = (int)min((int64_t)G, a.nframes - (int64_t)g * G);
+    const int64_t fstride = (int64_t)a.L * 2 * ES;   // bytes between frames of an input
+    // unit tid + 256 j: (input nl0 + 2 j, frame f, unit cu), since 256 units span
+    // two inputs' G frames.  Every load is issued (from a clamped, valid address)
+    // and its value dropped afterwards when it lies past the inputs or frames, so
+    // that no load waits behind a branch for the one before it.
+    static_assert(256 / UPF == 2 * G, "a pass of the workgroup covers two inputs");
+    const int cu = tid % UPF, f = (tid / UPF) % G, nl0 = tid / (UPF * G);
+    const int fr = min(f, fvalid - 1);
+    uint4 val[NB / 2];
 #pragma unroll
-    for (int j = 0; j < NB * G * UPF / 256; ++j) {
-        const int u = tid + 256 * j;
-        const int nl = u / (G * UPF), rem = u - nl * (G * UPF);
-        const int f = rem / UPF, cu = rem - f * UPF;
-        uint4 val = make_uint4(0u, 0u, 0u, 0u);
-        if (n0 + nl < a.n_in && f < fvalid)
-            val = *reinterpret_cast<const uint4 *>(
-                a.mid + (((int64_t)(n0 + nl) * a.mid_frames + a.frame0 + (int64_t)g * G + f) * a.L + c0) * 2 * ES +
-                cu * 16);
-        const uint8_t *b = reinterpret_cast<const uint8_t *>(&val);
-        const int re = row_re_off(f, ES), im = re + row_im_gap(ES);
+    for (int j = 0; j < NB / 2; ++j) {
+        const int n = min(n0 + nl0 + 2 * j, a.n_in - 1);
+        val[j] = *reinterpret_cast<const uint4 *>(
+            a.mid + ((int64_t)n * a.mid_frames + a.frame0 + (int64_t)g * G + fr) * fstride + (int64_t)c0 * 2 * ES +
+            cu * 16);
+    }
+    uint8_t *ldst = img + nl0 * NPITCH + f * FB + cu * 16;
 #pragma unroll
-        for (int e = 0; e < CPU; ++e) {
-            uint8_t *row = img + ((cu * CPU + e) * NB + nl) * kRowBytes;
-            if constexpr (ES == 1) {
-                row[re] = b[2 * e];
-                row[im] = b[2 * e + 1];
-            } else if constexpr (ES == 2) {
-                *reinterpret_cast<uint16_t *>(row + re) = *reinterpret_cast<const uint16_t *>(b + 4 * e);
-                *reinterpret_cast<uint16_t *>(row + im) = *reinterpret_cast<const uint16_t *>(b + 4 * e + 2);
-            } else {
-                *reinterpret_cast<uint32_t *>(row + re) = *reinterpret_cast<const uint32_t *>(b + 8 * e);
-                *reinterpret_cast<uint32_t *>(row + im) = *reinterpret_cast<const uint32_t *>(b + 8 * e + 4);
-            }
-        }
+    for (int j = 0; j < NB / 2; ++j) {
+        const bool in = n0 + nl0 + 2 * j < a.n_in && f < fvalid;
+        *reinterpret_cast<uint4 *>(ldst + j * 2 * NPITCH) = in ? val[j] : make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
+    const int nl = tid & 31;
+    if (n0 + nl >= a.n_in) return;
 #pragma unroll
-    for (int j = 0; j < CB * NB * 2 / 256; ++j) {
-        const int v = tid + 256 * j;
-        const int cl = v / (NB * 2), rem = v - cl * (NB * 2);
-        const int nl = rem >> 1, h = rem & 1;
-        if (n0 + nl < a.n_in) {
-            const uint4 val = *reinterpret_cast<const uint4 *>(img + (cl * NB + nl) * kRowBytes + h * 16);
-            *reinterpret_cast<uint4 *>(a.chan + ((((int64_t)(c0 + cl) * a.NG + a.grp0 + g) * a.n_in) + n0 + nl) *
-                                                    kRowBytes + h * 16) = val;
+    for (int t = 0; t < CB / 4 / 8; ++t) {
+        const int q = (tid >> 5) + 8 * t;      // channel quad of this lane
+        const uint8_t *src = img + nl * NPITCH + q * 8 * ES;
+        uint32_t w[4][8];                      // the four rows, as dwords
+        if constexpr (ES == 1) {
+            // frame f: (re, im) of channels 4q .. 4q + 3 in two dwords
+            uint2 r[16];
+#pragma unroll
+            for (int f = 0; f < 16; ++f) r[f] = *reinterpret_cast<const uint2 *>(src + f * FB);
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) {
+                const int wre = (fb >> 1) * 4 + (fb & 1), wim = wre + 2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // frames 4 fb .. 4 fb + 3 (A .. D) of channels 2h (bytes 0 = re,
+                    // 1 = im) and 2h + 1 (bytes 2, 3): a 4 x 4 byte transpose
+                    const uint32_t A = h ? r[4 * fb].y : r[4 * fb].x, B = h ? r[4 * fb + 1].y : r[4 * fb + 1].x;
+                    const uint32_t C = h ? r[4 * fb + 2].y : r[4 * fb + 2].x, D = h ? r[4 * fb + 3].y : r[4 * fb + 3].x;
+                    const uint32_t P = perm(B, A, 0x05010400u), Q = perm(B, A, 0x07030602u);   // A0 B0 A1 B1, A2 B2 A3 B3
+                    const uint32_t R = perm(D, C, 0x05010400u), S = perm(D, C, 0x07030602u);   // C0 D0 C1 D1, C2 D2 C3 D3
+                    w[2 * h][wre] = perm(R, P, 0x05040100u);
+                    w[2 * h][wim] = perm(R, P, 0x07060302u);
+                    w[2 * h + 1][wre] = perm(S, Q, 0x05040100u);
+                    w[2 * h + 1][wim] = perm(S, Q, 0x07060302u);
+                }
+            }
+        } else if constexpr (ES == 2) {
+            // frame f: one dword (re | im << 16) per channel
+            uint4 r[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) r[f] = *reinterpret_cast<const uint4 *>(src + f * FB);
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+                const int wre = (pp >> 1) * 4 + (pp & 1), wim = wre + 2;
+                const uint32_t X[4] = {r[2 * pp].x, r[2 * pp].y, r[2 * pp].z, r[2 * pp].w};
+                const uint32_t Y[4] = {r[2 * pp + 1].x, r[2 * pp + 1].y, r[2 * pp + 1].z, r[2 * pp + 1].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    w[k][wre] = (X[k] & 0xffffu) | (Y[k] << 16);
+                    w[k][wim] = (X[k] >> 16) | (Y[k] & 0xffff0000u);
+                }
+            }
+        } else {
+            // frame f: (re, im) of the four channels in eight dwords
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const uint4 lo = *reinterpret_cast<const uint4 *>(src + f * FB);
+                const uint4 hi = *reinterpret_cast<const uint4 *>(src + f * FB + 16);
+                w[0][f] = lo.x; w[0][4 + f] = lo.y;
+                w[1][f] = lo.z; w[1][4 + f] = lo.w;
+                w[2][f] = hi.x; w[2][4 + f] = hi.y;
+                w[3][f] = hi.z; w[3][4 + f] = hi.w;
+            }
+        }
+        uint8_t *dst = a.chan + (((int64_t)(c0 + 4 * q) * a.NG + a.grp0 + g) * a.n_in + n0 + nl) * kRowBytes;
+        const int64_t cstep = a.NG * a.n_in * kRowBytes;   // bytes between channels
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint4 *row = reinterpret_cast<uint4 *>(dst + k * cstep);
+            row[0] = make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
+            row[1] = make_uint4(w[k][4], w[k][5], w[k][6], w[k][7]);
         }
     }
 }
@@ -356,7 +415,9 @@ hipError_t launch_fft_xp(const FArgs &a, bool stats, int grid, hipStream_t s) {
 
 int fft6400_grid(int n_in, int64_t nframes, bool stats) {
     const int64_t items = (int64_t)n_in * nframes;
-    const int64_t cap = stats ? kStatsMaxWG : 8192;
+    // main pass: two rounds of the resident workgroups (two per CU, 256 CUs), so a
+    // workgroup loads its twiddles once for tens of frames
+    const int64_t cap = stats ? kStatsMaxWG : 1024;
     return (int)(items < cap ? items : cap);
 }
 
@@ -378,8 +439,8 @@ hipError_t launch_corner_turn(int esize, const CornerArgs &a, hipStream_t s) {
     const int64_t G = 16 / esize;
     const int64_t ngrp = (a.nframes + G - 1) / G;
     if (ngrp < 1) return hipSuccess;
-    if (a.L % 64 != 0 || ngrp > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)ngrp, (unsigned)(a.L / 64), (unsigned)((a.n_in + 15) / 16));
+    if (a.L % kCtChannels != 0 || ngrp > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)ngrp, (unsigned)(a.L / kCtChannels), (unsigned)((a.n_in + kCtInputs - 1) / kCtInputs));
     switch (esize) {
         case 1: hipLaunchKernelGGL(corner_turn_kernel<1>, grid, dim3(256), 0, s, a); break;
         case 2: hipLaunchKernelGGL(corner_turn_kernel<2>, grid, dim3(256), 0, s, a); break;
