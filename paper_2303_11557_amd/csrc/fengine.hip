@@ -710,13 +710,33 @@ __global__ void twiddle_kernel(float2 *tw, int L) {
     tw[k] = make_float2((float)cs, (float)sn);
 }
 
-// Scale of channel c from the partial rows of nwg workgroups ([nwg][L + 1]: L
-// power sums, then the populated-frame count), reduced in a fixed order so the
-// result is bitwise reproducible:
+// Scales of channel c from its power sum and populated-frame count over the
+// calibration window:
 //   sigma^2 = power / (2 populated),  s = 5 sigma / 127,  inv_s = 127 / (5 sigma)
 // (s = inv_s = 1 for a channel of zero power).  With no populated frame the
 // window holds only zeroed samples: the channel keeps last[] (the scales of the
 // plan's most recent calibrated integration).  Otherwise last[] is updated.
+__device__ __forceinline__ void finish_scale(double sum, double count, int L, float *scales, float *last, int c) {
+    float s = last[c], inv = last[L + c];
+    if (count > 0.0) {
+        const double var = sum / (2.0 * count);
+        s = 1.0f;
+        inv = 1.0f;
+        if (var > 0.0) {
+            const double sd = sqrt(var);
+            s = (float)(5.0 * sd / 127.0);
+            inv = (float)(127.0 / (5.0 * sd));
+        }
+        last[c] = s;
+        last[L + c] = inv;
+    }
+    scales[c] = s;
+    scales[L + c] = inv;
+}
+
+// Scales of channel c from the partial rows of nwg workgroups ([nwg][L + 1]: L
+// power sums, then the populated-frame count), reduced in a fixed order so the
+// result is bitwise reproducible.
 __device__ void calib_finish_channel(const double *stats, int nwg, int L, float *scales, float *last, int c) {
     __shared__ double part[256], cnt[256];
     __syncthreads();   // part/cnt of a previous call on this workgroup fully read
@@ -736,25 +756,58 @@ __device__ void calib_finish_channel(const double *stats, int nwg, int L, float 
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    float s = last[c], inv = last[L + c];
-    if (cnt[0] > 0.0) {
-        const double var = part[0] / (2.0 * cnt[0]);
-        s = 1.0f;
-        inv = 1.0f;
-        if (var > 0.0) {
-            const double sd = sqrt(var);
-            s = (float)(5.0 * sd / 127.0);
-            inv = (float)(127.0 / (5.0 * sd));
-        }
-        last[c] = s;
-        last[L + c] = inv;
-    }
-    scales[c] = s;
-    scales[L + c] = inv;
+    finish_scale(part[0], cnt[0], L, scales, last, c);
 }
 
 __global__ void calib_finish_kernel(const double *stats, int nwg, int L, float *scales, float *last) {
     calib_finish_channel(stats, nwg, L, scales, last, blockIdx.x);
+}
+
+// Wide transforms (L = 6400): one workgroup per 16 channels.  Thread (channel
+// cl, slice sl) sums the partial rows sl, sl + 16, ... into eight running sums
+// (row sl + 16 (8 k + i) into sum i, so eight loads are in flight); the eight
+// sums, then the sixteen slices (and the frame counts) are added in a fixed
+// order.
+constexpr int kWideCh = 16, kWideSl = 256 / kWideCh;
+__global__ __launch_bounds__(256) void calib_finish_wide_kernel(const double *stats, int nwg, int L, float *scales,
+                                                                float *last) {
+    constexpr int kAcc = 8;
+    __shared__ double part[kWideSl][kWideCh], cnt[kWideSl];
+    const int cl = threadIdx.x % kWideCh, sl = threadIdx.x / kWideCh, c = blockIdx.x * kWideCh + cl;
+    const int cc = c < L ? c : L;   // channels past L read the count column instead
+    double ts[kAcc] = {}, ns[kAcc] = {};
+    int w = sl;
+    for (; w + kWideSl * (kAcc - 1) < nwg; w += kWideSl * kAcc) {
+#pragma unroll
+        for (int i = 0; i < kAcc; ++i) {
+            ts[i] += stats[(int64_t)(w + kWideSl * i) * (L + 1) + cc];
+            ns[i] += stats[(int64_t)(w + kWideSl * i) * (L + 1) + L];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kAcc; ++i) {
+        if (w + kWideSl * i < nwg) {
+            ts[i] += stats[(int64_t)(w + kWideSl * i) * (L + 1) + cc];
+            ns[i] += stats[(int64_t)(w + kWideSl * i) * (L + 1) + L];
+        }
+    }
+    double t = 0.0, n = 0.0;
+#pragma unroll
+    for (int i = 0; i < kAcc; ++i) {
+        t += ts[i];
+        n += ns[i];
+    }
+    part[sl][cl] = t;
+    if (cl == 0) cnt[sl] = n;
+    __syncthreads();
+    if (sl != 0 || c >= L) return;
+    t = 0.0;
+    n = 0.0;
+    for (int k = 0; k < kWideSl; ++k) {
+        t += part[k][cl];
+        n += cnt[k];
+    }
+    finish_scale(t, n, L, scales, last, c);
 }
 
 // One workgroup per (channel, descriptor).  The descriptors of one instance are
@@ -905,7 +958,11 @@ hipError_t launch_twiddles(float2 *tw, int L, hipStream_t s) {
 }
 
 hipError_t launch_calib_finish(const double *stats, int nwg, int L, float *scales, float *last, hipStream_t s) {
-    hipLaunchKernelGGL(calib_finish_kernel, dim3(L), dim3(256), 0, s, stats, nwg, L, scales, last);
+    if (L == kUltraFineL)
+        hipLaunchKernelGGL(calib_finish_wide_kernel, dim3((L + kWideCh - 1) / kWideCh), dim3(256), 0, s, stats, nwg, L,
+                           scales, last);
+    else
+        hipLaunchKernelGGL(calib_finish_kernel, dim3(L), dim3(256), 0, s, stats, nwg, L, scales, last);
     return hipGetLastError();
 }
 

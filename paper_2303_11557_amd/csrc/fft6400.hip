@@ -416,8 +416,9 @@ hipError_t launch_fft_xp(const FArgs &a, bool stats, int grid, hipStream_t s) {
 int fft6400_grid(int n_in, int64_t nframes, bool stats) {
     const int64_t items = (int64_t)n_in * nframes;
     // main pass: two rounds of the resident workgroups (two per CU, 256 CUs), so a
-    // workgroup loads its twiddles once for tens of frames
-    const int64_t cap = stats ? kStatsMaxWG : 1024;
+    // workgroup loads its twiddles once for tens of frames; statistics pass: one
+    // round, so that the partial rows (6,401 doubles each) stay few
+    const int64_t cap = stats ? kStatsMaxWG / 2 : 1024;
     return (int)(items < cap ? items : cap);
 }
 
