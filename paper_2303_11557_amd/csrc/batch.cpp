@@ -30,7 +30,7 @@ using namespace mwax;
 namespace {
 
 constexpr int kMaxInstances = 64;
-constexpr int kMainGridCap = 65536;
+constexpr int kMainGridCap = 8192;    // F-engine workgroups per launch: tens of items each
 constexpr int kUnitOverheadGroups = 16;   // setup + flush of a tile item, in row-group units
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -401,6 +401,10 @@ std::vector<int32_t> block_ranges(const std::vector<int64_t> &work, int grid) {
     for (size_t d = 0; d < work.size(); ++d) {
         int64_t nb = 1 + (total > 0 ? spare * work[d] / total : 0);
         nb = std::min<int64_t>(nb, std::max<int64_t>(1, work[d]));
+        // whole rounds of the 8 XCDs: the F-engine then hands each XCD one
+        // contiguous range of items per round, so the output lines that adjacent
+        // items share are completed in one L2
+        if (nb >= 8) nb &= ~(int64_t)7;
         b0[d + 1] = (int32_t)(b0[d] + nb);
     }
     return b0;
