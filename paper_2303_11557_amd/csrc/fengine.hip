@@ -135,6 +135,12 @@ struct FCfg {
     // extra registers keep the occupancy)
     static constexpr bool PREFETCH = XP != MWAX_X_FP32 && L2 > 1 && (L <= 256 || XP == MWAX_X_INT8) && !DIRECT;
     static_assert(R >= 1 && NGWG * PPG == PACKS * R && (PPG == 1 || GPW == 1), "bad decomposition");
+    // workgroups of a single-plan launch (each takes items in rounds): enough that
+    // the workgroups holding adjacent items stay in step (their rows share output
+    // lines), few enough that each one's set-up is spread over tens of items.
+    // Measured at 256 tiles, 8 s: 65,536 at every length but 256, where 131,072
+    // is 10 % faster (32,768 - 262,144 swept).
+    static constexpr int64_t GRID_CAP = L == 256 ? 131072 : 65536;
 };
 
 // One complex int8 sample, converted exactly.  Written with arithmetic shifts of
@@ -604,7 +610,8 @@ hipError_t launch_L(const FArgs &a, hipStream_t s) {
     const bool stats = a.stats_mode != 0;
     if (a.R != C::R) return hipErrorInvalidValue;
     const int lds = fengine_lds_bytes(L, XP, a.R, stats);
-    const int grid = fengine_grid(a.n_in, a.R, a.ngrp, stats);
+    int grid = fengine_grid(a.n_in, a.R, a.ngrp, stats);
+    if (!stats) grid = (int)std::min<int64_t>((int64_t)a.ngrp * ((a.n_in + C::R - 1) / C::R), C::GRID_CAP);
     if (grid < 1) return hipSuccess;
     // allow dynamic LDS beyond the default limit (once per instantiation)
     const int variant = stats ? 1 : (a.dl ? 2 : 0);
