@@ -175,6 +175,8 @@ def parse():
     ap.add_argument("--stream-paced-rounds", type=int, default=15,
                     help="8 s blocks per channel over the host link: flat out, then real-time paced (15 = 120 s)")
     ap.add_argument("--stream-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
+    ap.add_argument("--stream-call-s", type=float, default=2.0,
+                    help="seconds of voltages per plan call (stream; 2 s = one integration)")
     ap.add_argument("--fft-len", type=int, default=L, help="channel workload: FFT length (default 128)")
     ap.add_argument("--ultra-modes", default="all", help="ultrafine: comma list of 40kHz_250ms,10kHz_1s,1kHz_8s")
     ap.add_argument("--steps", type=int, default=5)
@@ -724,7 +726,7 @@ def main_stream(args):
     mwax.lib()
     n_ch, n_tiles, Lc, tau = 24, 256, 128, 2.0
     block = int(SECONDS * F_S)
-    call = int(F_S)
+    call = int(args.stream_call_s * F_S)
     cfg = make_config(n_tiles, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=call)
     d = mwax.derive(cfg)
     n_in, P = d.n_inputs, d.n_pairs
@@ -794,7 +796,7 @@ def main_stream(args):
         "scaling": "weak", "vs_baseline": None, "dtype": args.xprec, "data": "synthetic",
         "config": {"workload": "24 channels x 256 tiles x 2 pols, continuous 8 s blocks of complex int8 "
                                "sigma=8 voltages + 1 source, 128-pt FFT, 2 s integrations on device, "
-                               "1 s plan calls, admission by HBM budget",
+                               f"{args.stream_call_s:g} s plan calls, admission by HBM budget",
                    "channels": n_ch, "block_samples": block, "pool_slots": info.pool_slots,
                    "hbm_budget_bytes": budget, "device_bytes": info.device_bytes},
         "rtf": dr["rtf"],
