@@ -175,6 +175,7 @@ def parse():
     ap.add_argument("--stream-paced-rounds", type=int, default=15,
                     help="8 s blocks per channel over the host link: flat out, then real-time paced (15 = 120 s)")
     ap.add_argument("--stream-budget-gb", type=float, default=64.0, help="HBM budget of the block pool")
+    ap.add_argument("--batch-call-s", type=float, default=BATCH_CALL_S, help="seconds of voltages per batch call")
     ap.add_argument("--stream-call-s", type=float, default=2.0,
                     help="seconds of voltages per plan call (stream; 2 s = one integration)")
     ap.add_argument("--fft-len", type=int, default=L, help="channel workload: FFT length (default 128)")
@@ -202,7 +203,7 @@ def main_batch(args):
     torch.cuda.set_device(0)
     mwax.lib()
     S = int(SECONDS * F_S)
-    chunk = int(BATCH_CALL_S * F_S)
+    chunk = int(args.batch_call_s * F_S)
     ncalls = S // chunk
     inst = batch_instances()
     cfgs = [make_config(t, L=Lc, int_time_s=tau, xprec=args.xprec, max_samples=chunk) for (t, Lc, tau) in inst]
@@ -287,7 +288,7 @@ def main_batch(args):
         "data": "synthetic",
         "config": {"workload": "24 instances: tiles {64,128,256} x 2 pols, FFT {32,128,1024}, integrations "
                                "{0.5,2,8} s (cycled), 8 s of complex int8 sigma=8 voltages + 1 source each, "
-                               "one batch, 1 s calls",
+                               f"one batch, {args.batch_call_s:g} s calls",
                    "instances": [list(x) for x in inst], "cmac_per_step": cmac_per_step,
                    "input_bytes": sum(v.numel() for v in volts)},
         "rtf": round(SECONDS / (ms / 1e3), 2),
