@@ -124,46 +124,97 @@ __global__ __launch_bounds__(256) void beamform_kernel(BeamArgs a) {
     }
 }
 
+// Power of the frames [f0, f1) of one 32-byte row (G frames of one input):
+// sum over those frames of re^2 + im^2.  INT8: exact, with signed 4-byte dot
+// products on the bytes kept by a per-dword mask (a dword holds the re or the
+// im parts of 4 frames); binary16 / FP32: FP64 sums of the exact squares.
+template <int ES>
+__device__ __forceinline__ double row_power(uint4 h0, uint4 h1, int f0, int f1) {
+    const uint32_t w[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+    if constexpr (ES == 1) {
+        // dword k: frames (k >> 2) * 8 + (k & 1) * 4 + 0 .. 3, re (k & 2 == 0) or im
+        int acc = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int fb = (k >> 2) * 8 + (k & 1) * 4;
+            uint32_t m = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m |= (fb + e >= f0 && fb + e < f1) ? (0xffu << (8 * e)) : 0u;
+            const int v = (int)(w[k] & m);
+            acc = __builtin_amdgcn_sdot4(v, v, acc, false);
+        }
+        return (double)acc;
+    } else if constexpr (ES == 2) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t >= f0 && t < f1) {
+                const float2 v = row_value<2>(reinterpret_cast<const uint8_t *>(w), t);
+                acc += (double)v.x * v.x + (double)v.y * v.y;
+            }
+        }
+        return acc;
+    } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= f0 && t < f1) {
+                const float2 v = row_value<4>(reinterpret_cast<const uint8_t *>(w), t);
+                acc += (double)v.x * v.x + (double)v.y * v.y;
+            }
+        }
+        return acc;
+    }
+}
+
 // One workgroup per output bin (o, j): channels o f_avg .. and spectra j t_avg
-// .. of the block; threads over inputs, FP64 sums per polarisation reduced in
-// a fixed order.  Per-channel scales are applied per channel (squared).
+// .. of the block.  The bin's spectra are walked segment by segment and row
+// group by row group; for each (row group, channel) the threads read whole
+// 32-byte rows of consecutive inputs (thread tid takes inputs tid, tid + 256,
+// .., all of one polarisation, so a wave reads 2 KB contiguous) and sum the
+// power of the frames inside the bin; each (row group, channel) sum is scaled
+// by the square of its channel's scale (INT8 s_c of the segment; binary16
+// 2^e) and added to the thread's FP64 total.  The totals are reduced per
+// polarisation in a fixed order.
 template <int ES>
 __global__ __launch_bounds__(256) void incoherent_kernel(IncohArgs a) {
     constexpr int G = 16 / ES;
-    __shared__ double red[2][256];
+    __shared__ double red[256];
     const int o = blockIdx.x;
     const int64_t j = blockIdx.y;
     const int tid = threadIdx.x;
-    double acc[2] = {0.0, 0.0};
-    for (int ci = 0; ci < a.f_avg; ++ci) {
-        const int c = o * a.f_avg + ci;
-        for (int64_t m = j * a.t_avg; m < (j + 1) * a.t_avg; ++m) {
-            // spectrum m of the block lies in segment s (its integration's scale)
-            int s = 0;
-            while (s + 1 < a.nseg && m >= a.seg_m0[s + 1]) ++s;
-            const int64_t t = m - a.seg_m0[s];
-            const double f = a.seg_scales[s] ? (double)a.seg_scales[s][c] * a.post : a.post;
-            double sp[2] = {0.0, 0.0};
-            for (int n = tid; n < a.n_in; n += 256) {
-                const uint8_t *row = a.chan + (((int64_t)c * a.NG + a.seg_grp0[s] + t / G) * a.n_in + n) * kRowBytes;
-                const float2 v = row_value<ES>(row, (int)(t % G));
-                sp[n & 1] += (double)v.x * v.x + (double)v.y * v.y;
+    const int64_t m_lo = j * a.t_avg, m_hi = m_lo + a.t_avg;   // block spectra of the bin
+    const int64_t m_end = a.n_j * a.t_avg;                       // block spectra
+    const int64_t rstride = (int64_t)a.n_in * kRowBytes;         // bytes between row groups
+    double acc = 0.0;
+    for (int s = 0; s < a.nseg; ++s) {
+        const int64_t s0 = a.seg_m0[s], s1 = s + 1 < a.nseg ? a.seg_m0[s + 1] : m_end;
+        const int64_t lo = m_lo > s0 ? m_lo : s0, hi = m_hi < s1 ? m_hi : s1;
+        if (lo >= hi) continue;
+        const int64_t t0 = lo - s0, t1 = hi - s0;                 // spectra of the segment
+        for (int64_t g = t0 / G; g * G < t1; ++g) {
+            const int f0 = (int)(t0 > g * G ? t0 - g * G : 0), f1 = (int)(t1 - g * G < G ? t1 - g * G : G);
+            for (int ci = 0; ci < a.f_avg; ++ci) {
+                const int c = o * a.f_avg + ci;
+                const uint8_t *rows = a.chan + ((int64_t)c * a.NG + a.seg_grp0[s] + g) * rstride;
+                double pw = 0.0;
+                for (int n = tid; n < a.n_in; n += 256) {
+                    const uint4 *r = reinterpret_cast<const uint4 *>(rows + (int64_t)n * kRowBytes);
+                    pw += row_power<ES>(r[0], r[1], f0, f1);
+                }
+                const double f = a.seg_scales[s] ? (double)a.seg_scales[s][c] * a.post : (double)a.post;
+                acc += pw * f * f;
             }
-            acc[0] += sp[0] * f * f;
-            acc[1] += sp[1] * f * f;
         }
     }
-    red[0][tid] = acc[0];
-    red[1][tid] = acc[1];
+    // inputs tid + 256 k have the polarisation tid & 1: even strides keep it
+    red[tid] = acc;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h) {
-            red[0][tid] += red[0][tid + h];
-            red[1][tid] += red[1][tid + h];
-        }
+    for (int h = 128; h > 1; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
         __syncthreads();
     }
-    if (tid < 2) a.out[(j * a.n_o + o) * 2 + tid] = (float)red[tid][0];
+    if (tid < 2) a.out[(j * a.n_o + o) * 2 + tid] = (float)red[tid];
 }
 
 }  // namespace
