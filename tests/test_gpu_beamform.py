@@ -96,19 +96,22 @@ def test_phased_tone_closed_form():
     assert np.abs(B[0, c0, 0]) ** 2 == pytest.approx(n * inc[0, 0].sum() / M, rel=1e-6)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "int8"])
-def test_incoherent_beam(prec):
-    n_tiles, L, M = 9, 64, 48
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "int8"])
+@pytest.mark.parametrize("n_tiles,L,M,t_avg,f_avg", [(9, 64, 48, 6, 8),
+                                                     # more inputs than threads; bins of 20 spectra
+                                                     # span two to three row groups
+                                                     (150, 16, 40, 20, 4)])
+def test_incoherent_beam(prec, n_tiles, L, M, t_avg, f_avg):
     n = 2 * n_tiles
-    v = synth.gaussian_volts(n, L * M, seed=910)
+    v = synth.gaussian_volts(n, L * M, seed=910 + n_tiles)
     v[1::2] = (v[1::2].astype(np.int16) // 2).astype(np.int8)       # Y paths quieter
     with Plan(make_config(n_tiles, L=L, T=M, xprec=prec, max_samples=L * M)) as p:
         p.channelise(torch.from_numpy(v).cuda())
-        got = p.beamform_incoherent(6, 8).cpu().numpy().astype(np.float64)
+        got = p.beamform_incoherent(t_avg, f_avg).cpu().numpy().astype(np.float64)
         s = p.get_scales().cpu().numpy().astype(np.float64) if prec == "int8" else None
         x = spectra_of(p, prec, None if s is None else np.broadcast_to(s, (M, L)))
-    want = oracle.incoherent(x, 6, 8)
-    assert got.shape == want.shape == (M // 6, L // 8, 2)
+    want = oracle.incoherent(x, t_avg, f_avg)
+    assert got.shape == want.shape == (M // t_avg, L // f_avg, 2)
     assert np.max(np.abs(got / want - 1)) < 1e-6
     assert np.all(got[..., 0] > 2 * got[..., 1])
 
